@@ -1,0 +1,217 @@
+/*
+ * pdf.h - C ABI of libpdfgpu.so: the particle time step of the non-hybrid PDF method
+ * (Bakosi, Franzese & Boybeyi, "A non-hybrid method for the PDF equations of turbulent
+ * flows on unstructured grids") on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (Secs. 2-3 of the paper) represents a turbulent flow by Lagrangian
+ * particles carrying position X, velocity U (3 components), turbulent frequency omega
+ * and a passive scalar psi.  An unstructured triangular grid supplies Eulerian fields at
+ * its nodes, locates particles and receives nodal statistics.  One explicit time step
+ * (Sec. 3.1, Table 1 without the two FEM solves, whose fields are inputs here):
+ *   1. interpolate the nodal fields to each particle with P1 shape functions (Eq. 37);
+ *   2. advance U by the generalized Langevin model (Eqs. 10/27, closure Eqs. 11, 18) and
+ *      omega by Eqs. (19)-(20), forward Euler;
+ *   3. move X by Eq. (7) and track it by the next-best-element walk (Sec. 3.6) with the
+ *      wall conditions of Sec. 3.8 and the scalar source of Sec. 4.1.2;
+ *   4. group particles by host element, build velocity bins by the sort-and-divide
+ *      procedure (Sec. 3.5, App. A) and mix psi by IECM (Eqs. 24-25);
+ *   5. reduce shape-function-weighted means and central second moments to the nodes
+ *      (Sec. 3.3).
+ * Particle-number control (Sec. 3.7, App. B) is a separate call.
+ *
+ * Conventions
+ *  - Every call returns a pdf_status; 0 is success.  On failure pdf_last_error() returns
+ *    a message for the calling thread.  No exception crosses the ABI.
+ *  - Input arrays are host pointers owned by the caller; the library copies what it needs
+ *    to the device during the call.  Handles own all device memory until destroyed.
+ *  - hip_stream is a hipStream_t (NULL = the default stream).  Work is enqueued on it in
+ *    order; calls that return host data synchronise that stream.
+ *  - Device-side failures (a particle that cannot be tracked, non-finite state, capacity
+ *    exhausted) are recorded in a sticky per-ensemble error word and returned by the next
+ *    synchronising call (pdf_stats, pdf_control, pdf_count, pdf_particles_export,
+ *    pdf_sync).  After such an error the ensemble must be destroyed.
+ *  - A handle is not thread-safe; different handles are independent.
+ *  - Symmetric tensors are stored as (11, 22, 33, 12, 13, 23).
+ */
+#ifndef PDF_H
+#define PDF_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdf_grid_s* pdf_grid;
+typedef struct pdf_ens_s* pdf_ens;
+typedef int32_t pdf_status;
+
+#define PDF_OK 0
+#define PDF_E_INVAL (-1)     /* bad argument */
+#define PDF_E_NOMEM (-2)     /* device or host allocation failed */
+#define PDF_E_HIP (-3)       /* HIP runtime error */
+#define PDF_E_MESH (-4)      /* invalid mesh (orientation, adjacency, boundary kinds) */
+#define PDF_E_CAPACITY (-5)  /* particle capacity exhausted */
+#define PDF_E_LOST (-6)      /* a particle could not be located after 64 moves */
+#define PDF_E_NONFINITE (-7) /* non-finite input field or particle state */
+#define PDF_E_STATE (-8)     /* call not valid in the current state */
+
+/* boundary kinds of element edges; edge k of a triangle is the edge opposite vertex k */
+enum { PDF_EDGE_INTERIOR = 0, PDF_EDGE_WALL = 1, PDF_EDGE_SLIP = 2, PDF_EDGE_PERIODIC = 3 };
+
+#define PDF_NSTAT 13     /* statistics per node, see pdf_stats */
+#define PDF_NCOUNTERS 8  /* event counters, see pdf_counters */
+#define PDF_NTIMERS 12   /* kernel timers, see pdf_timing */
+
+/* Unstructured P1 triangular mesh (Secs. 3.3-3.4, 3.6).
+ *  xy        [n_nodes][2] node coordinates.
+ *  tri       [n_elems][3] node ids, counter-clockwise.
+ *  edge_kind [n_elems][3] kind of the edge opposite vertex k.  Read only for edges that
+ *            belong to a single element, which must be PDF_EDGE_WALL (no-slip) or
+ *            PDF_EDGE_SLIP (free-slip).  Shared edges are classified by the library:
+ *            periodic when the two sides lie a period apart, interior otherwise.
+ *  period_x  > 0: x is periodic with this period; nodes lie in [0, period_x) and an
+ *            element spanning the seam references the nodes near x = 0.  0: not periodic. */
+typedef struct {
+    int64_t n_nodes;
+    const double* xy;
+    int64_t n_elems;
+    const int32_t* tri;
+    const uint8_t* edge_kind;
+    double period_x;
+} pdf_mesh_desc;
+
+/* Frozen Eulerian nodal fields (the outputs of the FEM solves of Sec. 3.2 and of the
+ * statistics of Sec. 3.3), each [n_nodes][k]:
+ *  grad_p [2]  mean pressure gradient d<P>/dx_i (divided by rho inside Eq. 27);
+ *  wp     [6]  elliptic-relaxation tensor of Eq. (11);
+ *  mean_u [3]  mean velocity <U_i>;
+ *  mean_omega [1] mean turbulent frequency <omega> (> 0);
+ *  rey    [6]  Reynolds stresses <u_i u_j> (trace > 0).
+ * The library derives the element gradients of <U_i> (Eqs. 39-40) and their nodal
+ * second derivatives by the two-pass averaging of Sec. 3.4. */
+typedef struct {
+    const double* grad_p;
+    const double* wp;
+    const double* mean_u;
+    const double* mean_omega;
+    const double* rey;
+} pdf_fields_desc;
+
+/* Model constants: viscosity nu, density rho, C3, C4, C_T, C_omega1, C_omega2 (Table 4)
+ * and C_s, C_t of the micromixing timescale, Eq. (25). */
+typedef struct {
+    double nu, rho, C3, C4, CT, Cw1, Cw2, Cs, Ct;
+} pdf_model;
+
+/* Particle set-up (Sec. 3.7, first paragraph) and per-ensemble options.
+ *  ppe            particles per element at set-up (uniform in each element);
+ *  u_sigma        standard deviation of the Gaussian initial velocity about <U>(x);
+ *  omega_shape    shape of the Gamma initial frequency about <omega>(x) (>= 1);
+ *  src_x, src_y, src_r   scalar source disk (Sec. 4.1.2); psi = 1 inside at set-up;
+ *  src_continuous 1: particles inside the disk after tracking get psi = 1 every step;
+ *  bins[3]        requested velocity bins per direction (Sec. 3.5), each >= 1;
+ *  min_per_bin    minimum particles per bin (>= 1; the paper uses 2);
+ *  precision      0 (FP64 throughout);
+ *  seed           seed of the counter-based generator;
+ *  capacity       particle slots to allocate (0: 2 x ppe x n_elems). */
+typedef struct {
+    int32_t ppe;
+    double u_sigma, omega_shape;
+    double src_x, src_y, src_r;
+    int32_t src_continuous;
+    int32_t bins[3];
+    int32_t min_per_bin;
+    int32_t precision;
+    uint64_t seed;
+    int64_t capacity;
+} pdf_init_desc;
+
+/* Result of pdf_control. */
+typedef struct {
+    int64_t live;    /* live particles after the call */
+    int64_t cloned;  /* particles added by splitting */
+    int64_t merged;  /* particles removed by merging */
+    int64_t empty;   /* elements without particles */
+    int64_t below;   /* elements that were below n_min */
+    int64_t above;   /* elements that were above n_max */
+} pdf_control_report;
+
+/* Build the device grid: validates the mesh (counter-clockwise, manifold, boundary kinds)
+ * and the fields (finite, <omega> > 0, k > 0), builds neighbours, element frames across the
+ * periodic seam, the elements around each node, wall lines of wall elements (Sec. 3.8),
+ * element gradients and nodal Laplacians of <U>, and uploads everything.
+ * Errors: PDF_E_INVAL, PDF_E_MESH, PDF_E_NONFINITE, PDF_E_NOMEM, PDF_E_HIP. */
+pdf_status pdf_grid_create(const pdf_mesh_desc* mesh, const pdf_fields_desc* fields,
+                           const pdf_model* model, void* hip_stream, pdf_grid* out);
+pdf_status pdf_grid_destroy(pdf_grid grid);
+
+/* Create an ensemble on grids[0] and seed ppe particles per element (Sec. 3.7): pid =
+ * e * ppe + k; initial element-grouping, binning and statistics are computed.
+ * n_problems must be 1.  Errors: PDF_E_INVAL, PDF_E_NOMEM, PDF_E_CAPACITY, PDF_E_HIP. */
+pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
+                              int32_t n_problems, void* hip_stream, pdf_ens* out);
+pdf_status pdf_ens_destroy(pdf_ens ens);
+
+/* Advance n_steps time steps of size dt[0] (> 0).  Enqueues only; does not synchronise. */
+pdf_status pdf_step(pdf_ens ens, const double* dt, int32_t n_steps, void* hip_stream);
+
+/* Nodal statistics of the last step (Sec. 3.3), out = [n_nodes][13]:
+ *   W = sum_p w_p N_n(x_p), <U1>, <U2>, <U3>, <omega>, <psi>,
+ *   <u1u1>, <u2u2>, <u3u3>, <u1u2>, <u1u3>, <u2u3>, <psi'psi'>
+ * over the particles of the elements around node n, weighted by w_p N_n(x_p); the
+ * second moments are about the node's own means (NaN where W = 0).
+ * out_is_device != 0: out is a device pointer and the copy is enqueued on hip_stream;
+ * otherwise out is host memory and the call synchronises. */
+pdf_status pdf_stats(pdf_ens ens, int32_t problem, double* out, int32_t out_is_device,
+                     void* hip_stream);
+
+/* Per-element particle-number control (Sec. 3.7, App. B) on the canonical order of the
+ * last step: elements with 0 < n < n_min split min(n_min - n, n) particles into two
+ * half-weight copies; elements with n > n_max merge pairs of particles of one velocity
+ * bin into their weighted average, up to n - n_max merges.  Conserves the total weight and
+ * the weighted sums of U, omega and psi in every element and bin.  Synchronises and fills
+ * report when it is not NULL.  Errors: PDF_E_INVAL (n_min > n_max, n_max < 1),
+ * PDF_E_CAPACITY, PDF_E_HIP. */
+pdf_status pdf_control(pdf_ens ens, int32_t n_min, int32_t n_max, pdf_control_report* report,
+                       void* hip_stream);
+
+/* Live particles (synchronises). */
+pdf_status pdf_count(pdf_ens ens, int32_t problem, int64_t* live);
+
+/* Copy the live particles to host arrays of at least cap entries (any pointer may be
+ * NULL): x, y, u [n][3], omega, psi, weight, pid, host element.  *n_out = live count.
+ * Order: element-grouped, canonical within elements after a step.  Synchronises. */
+pdf_status pdf_particles_export(pdf_ens ens, int32_t problem, int64_t cap, double* x, double* y,
+                                double* u, double* omega, double* psi, double* w,
+                                uint64_t* pid, int32_t* elem, int64_t* n_out, void* hip_stream);
+
+/* Replace the particle state with n host-side particles (elem must be each particle's host
+ * element); sets the step counter and the next pid, then recomputes grouping, bins and
+ * statistics without mixing.  Synchronises.  Errors: PDF_E_INVAL, PDF_E_CAPACITY. */
+pdf_status pdf_particles_import(pdf_ens ens, int32_t problem, int64_t n, const double* x,
+                                const double* y, const double* u, const double* omega,
+                                const double* psi, const double* w, const uint64_t* pid,
+                                const int32_t* elem, int64_t step, uint64_t next_pid,
+                                void* hip_stream);
+
+/* Event counters since set-up (synchronises): wall (a), wall (b), reflections, fall-back
+ * searches, omega reflections, C0 clamps, walk moves, source hits. */
+pdf_status pdf_counters(pdf_ens ens, int32_t problem, int64_t out[PDF_NCOUNTERS]);
+
+/* Kernel timing with HIP events on the ensemble's stream.  enable = 1 starts (and resets)
+ * recording, 0 stops.  ms_out[PDF_NTIMERS] (may be NULL) receives the summed durations and
+ * launches_out[PDF_NTIMERS] the launch counts, in the order: init, advance, scan,
+ * scatter, element pass, node finalize, control plan, control scan, control apply, fill,
+ * count, other.  Synchronises when reading. */
+pdf_status pdf_timing(pdf_ens ens, int32_t enable, double* ms_out, int64_t* launches_out);
+
+/* Wait for the ensemble's work and return its sticky device error, if any. */
+pdf_status pdf_sync(pdf_ens ens);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* pdf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,967 @@
+// Kernels of libpdfgpu (gfx950).  One time step is
+//   k_advance      per particle: P1 interpolation, GLM velocity and frequency SDEs, move,
+//                  next-best-element walk with wall conditions, source; counts particles
+//                  per new host element (wavefront-aggregated atomics)
+//   k_scan_*       exclusive scan of the counts -> element segment starts
+//   k_scatter      per particle: slot inside its element's segment (grouping by element)
+//   k_element_pass per element: sort-and-divide velocity binning in LDS, bin means, IECM
+//                  mixing, shape-weighted partial sums per vertex, write the element's
+//                  particles in canonical order into the other state buffer
+//   k_node_finalize per node: fixed-order sum of the vertex partials -> statistics
+// and number control is k_ctl_plan (merges), a scan, and k_ctl_apply (splits).
+#include "device.h"
+#include "kernels.h"
+
+namespace pdfgpu {
+
+// =====================================================================================
+// advance + track (Eqs. 7, 10/27, 11, 18-20; Secs. 3.6, 3.8, 4.1.2)
+// =====================================================================================
+
+// fall-back search of Sec. 3.6 (Fig. 2): elements around the nodes of element c, nodes in
+// vertex order, elements ascending; returns the first that contains P and the x offset
+// into its frame
+__device__ __noinline__ bool fallback_search(const ElemGeo* __restrict__ geo, const int64_t* __restrict__ n2e_ptr,
+                                             const int32_t* __restrict__ n2e, int32_t c, double x, double y,
+                                             int32_t& found, double& off)
+{
+    const ElemGeo* G = geo + c;
+    for (int v = 0; v < 3; ++v) {
+        const int32_t node = G->node[v];
+        const int64_t j0 = n2e_ptr[node], j1 = n2e_ptr[node + 1];
+        for (int64_t j = j0; j < j1; ++j) {
+            const int32_t ent = n2e[j];
+            const int32_t fe = ent / 3, slot = ent - 3 * fe;
+            if (fe == c) continue;
+            const double o = geo[fe].x[slot] - G->x[v];
+            double na, nb, nc;
+            area_coords(geo + fe, x + o, y, na, nb, nc);
+            if (na >= 0.0 && nb >= 0.0 && nc >= 0.0) {
+                found = fe;
+                off = o;
+                return true;
+            }
+        }
+    }
+    return false;
+}
+
+__global__ void __launch_bounds__(256) k_advance(AdvanceArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nslots = *a.nslots;
+    int32_t key = -1;
+    int ev_a = 0, ev_b = 0, omrefl = 0, clamp = 0, src = 0, steps = 0, refl = 0, fb = 0;
+    if (i < nslots) {
+        int32_t e = a.s.elem[i];
+        if (e >= a.ne) {
+            atomicOr(a.err, ERR_BADELEM);
+            e = -1;
+        }
+        if (e >= 0) {
+            const ModelC& m = a.m;
+            const ElemGeo* G = a.geo + e;
+            const double x0 = a.s.x[i], y0 = a.s.y[i];
+            const double u0 = a.s.u0[i], u1 = a.s.u1[i], u2 = a.s.u2[i];
+            const double om = a.s.om[i];
+            const uint64_t pid = a.s.pid[i];
+
+            // (a1) P1 interpolation of the nodal fields (Eq. 37)
+            double na, nb, nc;
+            area_coords(G, x0, y0, na, nb, nc);
+            const double la = na / G->area, lb = nb / G->area, lc = nc / G->area;
+            const double* __restrict__ FA = a.node + (int64_t)G->node[0] * NODE_STRIDE;
+            const double* __restrict__ FB = a.node + (int64_t)G->node[1] * NODE_STRIDE;
+            const double* __restrict__ FC = a.node + (int64_t)G->node[2] * NODE_STRIDE;
+            double f[21];
+#pragma unroll
+            for (int q = 0; q < 21; ++q) f[q] = la * FA[q] + lb * FB[q] + lc * FC[q];
+            const double gu0 = G->gu[0], gu1 = G->gu[1], gu2 = G->gu[2], gu3 = G->gu[3], gu4 = G->gu[4],
+                         gu5 = G->gu[5];
+
+            // (a2) closure (Eqs. 11, 18, 20)
+            const double R11 = f[NF_RE], R22 = f[NF_RE + 1], R33 = f[NF_RE + 2];
+            const double R12 = f[NF_RE + 3], R13 = f[NF_RE + 4], R23 = f[NF_RE + 5];
+            const double W11 = f[NF_WP], W22 = f[NF_WP + 1], W33 = f[NF_WP + 2];
+            const double W12 = f[NF_WP + 3], W13 = f[NF_WP + 4], W23 = f[NF_WP + 5];
+            const double k = 0.5 * (R11 + R22 + R33);
+            const double Om = f[NF_OM];
+            const double eps = Om * (k + m.nu * m.CT * m.CT * Om);
+            const double wpR = W11 * R11 + W22 * R22 + W33 * R33 + 2.0 * (W12 * R12 + W13 * R13 + W23 * R23);
+            double c0eps = -2.0 * wpR / (3.0 * k);
+            if (c0eps < 0.0) {
+                c0eps = 0.0;
+                clamp = 1;
+            }
+            const double prod = -(R11 * gu0 + R12 * gu1 + R12 * gu2 + R22 * gu3 + R13 * gu4 + R23 * gu5);
+            const double Sw = m.Cw2 - m.Cw1 * prod / eps;
+            const double ik = 1.0 / k;
+            const double G11 = (W11 - 0.5 * eps) * ik, G22 = (W22 - 0.5 * eps) * ik, G33 = (W33 - 0.5 * eps) * ik;
+            const double G12 = W12 * ik, G13 = W13 * ik, G23 = W23 * ik;
+
+            // random numbers: 6 Gaussians and one uniform (Sec. 3.9)
+            const Words4 wA = rng_draw(a.key, pid, a.step, TAG_STEP, 0);
+            const Words4 wB = rng_draw(a.key, pid, a.step, TAG_STEP, 1);
+            double z0, z1, z2, z3, z4, z5;
+            box_muller(wA.w0, wA.w1, z0, z1);
+            box_muller(wA.w2, wA.w3, z2, z3);
+            box_muller(wB.w0, wB.w1, z4, z5);
+            const double sdt = sqrt(a.dt);
+            const double dWx = sdt * z0, dWy = sdt * z1;
+            const double dWp0 = sdt * z2, dWp1 = sdt * z3, dWp2 = sdt * z4, dWo = sdt * z5;
+            const double eta = u01(wB.w2);
+            const double s2nu = sqrt(2.0 * m.nu);
+            const double sc0 = sqrt(c0eps);
+
+            // velocity, Eq. (27)
+            const double d0 = u0 - f[NF_MU], d1 = u1 - f[NF_MU + 1], d2 = u2 - f[NF_MU + 2];
+            const double irho = 1.0 / m.rho;
+            const double dr0 = -f[NF_GP] * irho + 2.0 * m.nu * f[NF_LAP] + G11 * d0 + G12 * d1 + G13 * d2;
+            const double dr1 = -f[NF_GP + 1] * irho + 2.0 * m.nu * f[NF_LAP + 1] + G12 * d0 + G22 * d1 + G23 * d2;
+            const double dr2 = 2.0 * m.nu * f[NF_LAP + 2] + G13 * d0 + G23 * d1 + G33 * d2;
+            double v0 = u0 + dr0 * a.dt + s2nu * (gu0 * dWx + gu1 * dWy) + sc0 * dWp0;
+            double v1 = u1 + dr1 * a.dt + s2nu * (gu2 * dWx + gu3 * dWy) + sc0 * dWp1;
+            double v2 = u2 + dr2 * a.dt + s2nu * (gu4 * dWx + gu5 * dWy) + sc0 * dWp2;
+            // frequency, Eq. (19): |omega| in the diffusion, reflected at zero
+            double omn = om - m.C3 * Om * (om - Om) * a.dt - Sw * Om * om * a.dt +
+                         sqrt(2.0 * m.C3 * m.C4 * Om * Om * fabs(om)) * dWo;
+            if (omn < 0.0) {
+                omn = -omn;
+                omrefl = 1;
+            }
+            // position, Eq. (7), with the start-of-step velocity
+            double x = x0 + u0 * a.dt + s2nu * dWx;
+            double y = y0 + u1 * a.dt + s2nu * dWy;
+
+            // (a3) next-best-element walk (Sec. 3.6) with particle wall conditions (Sec. 3.8)
+            int32_t c = e;
+            double shift = 0.0;
+            bool found = false;
+            int wall_a = 0;
+            for (int it = 0; it < 64; ++it) {
+                const ElemGeo* C = a.geo + c;
+                double ma, mb, mc;
+                area_coords(C, x, y, ma, mb, mc);
+                if (ma >= 0.0 && mb >= 0.0 && mc >= 0.0) {
+                    found = true;
+                    break;
+                }
+                int kk = 0;
+                double mn = ma;
+                if (mb < mn) {
+                    kk = 1;
+                    mn = mb;
+                }
+                if (mc < mn) kk = 2;
+                const uint8_t kd = C->kind[kk];
+                if (kd == KIND_INTERIOR) {
+                    c = C->nbr[kk];
+                    ++steps;
+                    continue;
+                }
+                if (kd == KIND_PERIODIC) {
+                    x += C->shift[kk];
+                    shift += C->shift[kk];
+                    c = C->nbr[kk];
+                    ++steps;
+                    continue;
+                }
+                int32_t fe;
+                double off;
+                if (fallback_search(a.geo, a.n2e_ptr, a.n2e, c, x, y, fe, off)) {
+                    c = fe;
+                    x += off;
+                    shift += off;
+                    ++fb;
+                    continue;
+                }
+                if (refl == 4) break;
+                // mirror across the line of edge kk (vertex kk+1 -> kk+2, interior on the left)
+                const int pa = (kk + 1) % 3, pb = (kk + 2) % 3;
+                const double ax = C->x[pa], ay = C->y[pa];
+                const double ex = C->x[pb] - ax, ey = C->y[pb] - ay;
+                const double len = sqrt(ex * ex + ey * ey);
+                const double nx = -ey / len, ny = ex / len;
+                const double dd = (x - ax) * nx + (y - ay) * ny;
+                x = x - 2.0 * dd * nx;
+                y = y - 2.0 * dd * ny;
+                if (kd == KIND_WALL) {
+                    wall_a = 1;
+                } else {
+                    const double un = v0 * nx + v1 * ny;
+                    v0 = v0 - 2.0 * un * nx;
+                    v1 = v1 - 2.0 * un * ny;
+                }
+                ++refl;
+            }
+            if (!found) {
+                atomicOr(a.err, ERR_LOST);
+                key = e;   // the particle keeps its start-of-step state
+            } else {
+                // no-slip events: (a) crossed the wall; (b) Eq. (53) in wall elements
+                bool hit = wall_a != 0;
+                const ElemGeo* C = a.geo + c;
+                if (!hit && C->wall && m.nu * a.dt > 0.0) {
+                    double dn = (x0 + shift - C->wl[0]) * C->wl[2] + (y0 - C->wl[1]) * C->wl[3];
+                    double dn1 = (x - C->wl[0]) * C->wl[2] + (y - C->wl[1]) * C->wl[3];
+                    dn = dn < 0.0 ? 0.0 : dn;
+                    dn1 = dn1 < 0.0 ? 0.0 : dn1;
+                    const double fw = exp(-dn * dn1 / (m.nu * a.dt));
+                    if (eta < fw) {
+                        hit = true;
+                        ev_b = 1;
+                    }
+                }
+                if (hit) {
+                    ev_a = wall_a;
+                    double pa_, pb_, pc_;
+                    area_coords(C, x, y, pa_, pb_, pc_);
+                    const double* __restrict__ HA = a.node + (int64_t)C->node[0] * NODE_STRIDE;
+                    const double* __restrict__ HB = a.node + (int64_t)C->node[1] * NODE_STRIDE;
+                    const double* __restrict__ HC = a.node + (int64_t)C->node[2] * NODE_STRIDE;
+                    const double omw = (pa_ / C->area) * HA[NF_OM] + (pb_ / C->area) * HB[NF_OM] +
+                                       (pc_ / C->area) * HC[NF_OM];
+                    v0 = v1 = v2 = 0.0;
+                    omn = gamma_draw(1.0 / m.C4, omw, a.key, pid, a.step, TAG_WALL_GAMMA);
+                }
+                a.s.x[i] = x;
+                a.s.y[i] = y;
+                a.s.u0[i] = v0;
+                a.s.u1[i] = v1;
+                a.s.u2[i] = v2;
+                a.s.om[i] = omn;
+                a.s.elem[i] = c;
+                if (a.src_cont) {
+                    double dx = x - a.src_x, dy = y - a.src_y;
+                    if (a.period > 0.0) {
+                        if (dx > 0.5 * a.period) dx -= a.period;
+                        else if (dx < -0.5 * a.period) dx += a.period;
+                    }
+                    if (dx * dx + dy * dy < a.src_r2) {
+                        a.s.psi[i] = 1.0;
+                        src = 1;
+                    }
+                }
+                if (!(isfinite(x) && isfinite(y) && isfinite(v0) && isfinite(v1) && isfinite(v2) && isfinite(omn)))
+                    atomicOr(a.err, ERR_NONFINITE);
+                key = c;
+            }
+        }
+    }
+    // (a4, first half) particles per new host element: runs of equal keys share one atomic
+    int leader, len, rank;
+    wave_runs(key, leader, len, rank);
+    if (rank == 0 && key >= 0) atomicAdd(a.counts + key, len);
+
+    // event counters
+    const int lane = lane_id();
+    const int c_a = __popcll(__ballot(ev_a != 0)), c_b = __popcll(__ballot(ev_b != 0));
+    const int c_o = __popcll(__ballot(omrefl != 0)), c_c = __popcll(__ballot(clamp != 0));
+    const int c_s = __popcll(__ballot(src != 0));
+    const unsigned long long anymove = __ballot(steps != 0 || refl != 0 || fb != 0);
+    int s_steps = 0, s_refl = 0, s_fb = 0;
+    if (anymove) {
+        s_steps = wave_sum_int(steps);
+        s_refl = wave_sum_int(refl);
+        s_fb = wave_sum_int(fb);
+    }
+    if (lane == 0) {
+        if (c_a) atomicAdd(a.cnt + 0, (unsigned long long)c_a);
+        if (c_b) atomicAdd(a.cnt + 1, (unsigned long long)c_b);
+        if (s_refl) atomicAdd(a.cnt + 2, (unsigned long long)s_refl);
+        if (s_fb) atomicAdd(a.cnt + 3, (unsigned long long)s_fb);
+        if (c_o) atomicAdd(a.cnt + 4, (unsigned long long)c_o);
+        if (c_c) atomicAdd(a.cnt + 5, (unsigned long long)c_c);
+        if (s_steps) atomicAdd(a.cnt + 6, (unsigned long long)s_steps);
+        if (c_s) atomicAdd(a.cnt + 7, (unsigned long long)c_s);
+    }
+}
+
+// =====================================================================================
+// grouping by element: count (for set-up/import), scan, scatter
+// =====================================================================================
+__global__ void __launch_bounds__(256) k_count(const int32_t* __restrict__ elem, const int64_t* __restrict__ nslots,
+                                               int64_t ne, int32_t* __restrict__ counts, uint32_t* __restrict__ err)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int32_t key = -1;
+    if (i < *nslots) {
+        key = elem[i];
+        if (key >= ne) {
+            atomicOr(err, ERR_BADELEM);
+            key = -1;
+        }
+    }
+    int leader, len, rank;
+    wave_runs(key, leader, len, rank);
+    if (rank == 0 && key >= 0) atomicAdd(counts + key, len);
+}
+
+constexpr int SCAN_NT = 256, SCAN_IPT = 8, SCAN_TILE = SCAN_NT * SCAN_IPT;
+
+// block-wide exclusive scan of one int per thread; returns the block total
+__device__ __forceinline__ int block_exclusive_scan(int v, int& total)
+{
+    __shared__ int wsum[SCAN_NT / 64];
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, (unsigned)o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_NT / 64; ++w) {
+        if (w < wid) base += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    total = tot;
+    return base + inc - v;
+}
+
+__global__ void __launch_bounds__(SCAN_NT) k_scan_reduce(const int32_t* __restrict__ in, int64_t n,
+                                                         int32_t* __restrict__ bsum)
+{
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    int s = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_IPT; ++q)
+        if (base + q < n) s += in[base + q];
+    int total;
+    (void)block_exclusive_scan(s, total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// exclusive scan of nb block sums in place (single block; nb <= SCAN_TILE)
+__global__ void __launch_bounds__(SCAN_NT) k_scan_top(int32_t* __restrict__ bsum, int64_t nb)
+{
+    const int64_t base = (int64_t)threadIdx.x * SCAN_IPT;
+    int v[SCAN_IPT];
+    int s = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_IPT; ++q) {
+        v[q] = (base + q < nb) ? bsum[base + q] : 0;
+        s += v[q];
+    }
+    int total;
+    int run = block_exclusive_scan(s, total);
+#pragma unroll
+    for (int q = 0; q < SCAN_IPT; ++q) {
+        if (base + q < nb) bsum[base + q] = run;
+        run += v[q];
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const int32_t* __restrict__ in, int64_t n,
+                                                        const int32_t* __restrict__ bsum, int32_t* __restrict__ out,
+                                                        int64_t nb)
+{
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    int v[SCAN_IPT];
+    int s = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_IPT; ++q) {
+        v[q] = (base + q < n) ? in[base + q] : 0;
+        s += v[q];
+    }
+    int total;
+    int run = block_exclusive_scan(s, total) + bsum[blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < SCAN_IPT; ++q) {
+        if (base + q < n) out[base + q] = run;
+        run += v[q];
+    }
+    if (blockIdx.x == nb - 1 && threadIdx.x == SCAN_NT - 1) out[n] = run;
+}
+
+// slot of every live particle inside its element's segment; the counts return to zero
+__global__ void __launch_bounds__(256) k_scatter(const int32_t* __restrict__ elem, const int64_t* __restrict__ nslots,
+                                                 int64_t ne, int32_t* __restrict__ counts,
+                                                 const int32_t* __restrict__ start, int32_t* __restrict__ idx,
+                                                 uint32_t* __restrict__ err)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int32_t key = -1;
+    if (i < *nslots) {
+        key = elem[i];
+        if (key >= ne) key = -1;
+    }
+    int leader, len, rank;
+    wave_runs(key, leader, len, rank);
+    int base = 0;
+    if (rank == 0 && key >= 0) base = atomicSub(counts + key, len) - len;
+    base = __shfl(base, leader);
+    if (key >= 0) {
+        const int64_t lo = start[key], hi = start[key + 1];
+        const int64_t slot = lo + (int64_t)base + rank;
+        if (slot >= lo && slot < hi) idx[slot] = (int32_t)i;
+        else atomicOr(err, ERR_BADELEM);
+    }
+}
+
+// =====================================================================================
+// element pass (Sec. 3.5, App. A, Eqs. 24-25; Sec. 3.3)
+// =====================================================================================
+// (velocity component, pid) as a pair of integers whose lexicographic order is the
+// order of the doubles (-0 is first folded onto +0); a strict total order for any bits
+struct SortKey {
+    uint64_t k;
+    uint64_t p;
+};
+__device__ __forceinline__ uint64_t order_bits(double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v + 0.0);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ bool key_less(const SortKey& a, uint64_t bk, uint64_t bp)
+{
+    return a.k < bk || (a.k == bk && a.p < bp);
+}
+
+// groups per level of the sort-and-divide procedure (see the oracle's reading)
+__device__ __forceinline__ int bin_structure(int n, int b0, int b1, int b2, int m, int& g0, int& g1, int& g2)
+{
+    const int bl[3] = {b0, b1, b2};
+    int g[3];
+    long long P = 1;
+    bool stopped = false;
+    for (int l = 0; l < 3; ++l) {
+        long long q = (long long)n / ((long long)m * P);
+        if (q < 1) q = 1;
+        long long gl = bl[l] < q ? bl[l] : q;
+        if (stopped) gl = 1;
+        if (gl < bl[l]) stopped = true;
+        g[l] = (int)gl;
+        P *= gl;
+    }
+    g0 = g[0];
+    g1 = g[1];
+    g2 = g[2];
+    return (int)P;
+}
+
+// keeps a load index inside [0, n): ranks are unique for unique pids, this only guards
+// memory safety against corrupted input
+__device__ __forceinline__ int clampi(int j, int n) { return j < 0 ? 0 : (j >= n ? n - 1 : j); }
+
+template <int NT>
+__device__ __forceinline__ void element_body(const ElementArgs& a, int32_t e, int64_t s0, int n, double* U0,
+                                             double* U1, double* U2, uint64_t* PID, SortKey* kp, int32_t* ordA,
+                                             int32_t* ordB, double* bmean, double* red)
+{
+    const int tid = threadIdx.x;
+    // load velocities and pids of the element's particles (load order j)
+    for (int j = tid; j < n; j += NT) {
+        const int64_t gi = a.idx[s0 + j];
+        U0[j] = a.in.u0[gi];
+        U1[j] = a.in.u1[gi];
+        U2[j] = a.in.u2[gi];
+        PID[j] = a.in.pid[gi];
+        ordA[j] = j;
+    }
+    __syncthreads();
+    int g0, g1, g2;
+    const int Cp = bin_structure(n, a.bins0, a.bins1, a.bins2, a.minpb, g0, g1, g2);
+    const int gl[3] = {g0, g1, g2};
+    // three levels: sort every group of the previous level by (U_l, pid) (rank sort)
+    long long C = 1;
+    for (int l = 0; l < 3; ++l) {
+        const double* Ul = l == 0 ? U0 : (l == 1 ? U1 : U2);
+        for (int pos = tid; pos < n; pos += NT) {
+            const int j = clampi(ordA[pos], n);
+            kp[pos].k = order_bits(Ul[j]);
+            kp[pos].p = PID[j];
+        }
+        __syncthreads();
+        for (int pos = tid; pos < n; pos += NT) {
+            const long long t = C * pos / n;
+            const int lo = (int)((t * n + C - 1) / C), hi = (int)(((t + 1) * n + C - 1) / C);
+            const uint64_t mk = kp[pos].k;
+            const uint64_t mp = kp[pos].p;
+            int r = 0;
+            for (int q = lo; q < hi; ++q) r += key_less(kp[q], mk, mp) ? 1 : 0;
+            ordB[lo + (r < hi - lo ? r : hi - lo - 1)] = ordA[pos];
+        }
+        __syncthreads();
+        int32_t* t = ordA;
+        ordA = ordB;
+        ordB = t;
+        C *= gl[l];
+    }
+    // bin means of psi, weighted (App. A)
+    double* wacc = reinterpret_cast<double*>(kp);
+    for (int pos = tid; pos < n; pos += NT) {
+        const int64_t gi = a.idx[s0 + clampi(ordA[pos], n)];
+        const double w = a.in.w[gi];
+        wacc[2 * pos] = w * a.in.psi[gi];
+        wacc[2 * pos + 1] = w;
+    }
+    __syncthreads();
+    for (int b = tid; b < Cp; b += NT) {
+        const int lo = (int)(((long long)b * n + Cp - 1) / Cp), hi = (int)(((long long)(b + 1) * n + Cp - 1) / Cp);
+        double sw = 0.0, swp = 0.0;
+        for (int q = lo; q < hi; ++q) {
+            swp += wacc[2 * q];
+            sw += wacc[2 * q + 1];
+        }
+        bmean[b] = swp / sw;
+    }
+    __syncthreads();
+
+    // IECM (Eq. 24) with f = min(dt / t_m, 1); statistics partials; canonical write-out
+    double fmix = a.dt / a.tm[e];
+    fmix = fmix > 1.0 ? 1.0 : fmix;
+    const ElemGeo* G = a.geo + e;
+    double rs[3][5];
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) rs[v][q] = a.shift[(int64_t)G->node[v] * 5 + q];
+    double acc[3][NPART];
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int q = 0; q < NPART; ++q) acc[v][q] = 0.0;
+    for (int pos = tid; pos < n; pos += NT) {
+        const int j = clampi(ordA[pos], n);
+        const int64_t gi = a.idx[s0 + j];
+        const double x = a.in.x[gi], y = a.in.y[gi];
+        const double w = a.in.w[gi], om = a.in.om[gi];
+        double psi = a.in.psi[gi];
+        const double u0 = U0[j], u1 = U1[j], u2 = U2[j];
+        const int b = (int)(((long long)Cp * pos) / n);
+        psi = psi - fmix * (psi - bmean[b]);
+        const int64_t o = s0 + pos;
+        a.out.x[o] = x;
+        a.out.y[o] = y;
+        a.out.u0[o] = u0;
+        a.out.u1[o] = u1;
+        a.out.u2[o] = u2;
+        a.out.om[o] = om;
+        a.out.psi[o] = psi;
+        a.out.w[o] = w;
+        a.out.pid[o] = PID[j];
+        a.out.elem[o] = e;
+        double na, nb, nc;
+        area_coords(G, x, y, na, nb, nc);
+        const double lam[3] = {na / G->area, nb / G->area, nc / G->area};
+        const double q5[5] = {u0, u1, u2, om, psi};
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const double wl = w * lam[v];
+            double d[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) d[q] = q5[q] - rs[v][q];
+            acc[v][0] += wl;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) acc[v][1 + q] += wl * d[q];
+            acc[v][6] += wl * d[0] * d[0];
+            acc[v][7] += wl * d[1] * d[1];
+            acc[v][8] += wl * d[2] * d[2];
+            acc[v][9] += wl * d[0] * d[1];
+            acc[v][10] += wl * d[0] * d[2];
+            acc[v][11] += wl * d[1] * d[2];
+            acc[v][12] += wl * d[4] * d[4];
+        }
+    }
+    // fixed-order reduction: butterfly inside each wavefront, then waves in order
+    const int lane = lane_id(), wid = tid >> 6;
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int q = 0; q < NPART; ++q) {
+            const double s = wave_sum_double(acc[v][q]);
+            if (lane == 0) red[wid * 3 * NPART + v * NPART + q] = s;
+        }
+    __syncthreads();
+    if (tid < 3 * NPART) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w * 3 * NPART + tid];
+        a.part[(int64_t)e * 3 * NPART + tid] = s;
+    }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_element_pass(ElementArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int32_t e = (int32_t)blockIdx.x;
+    if (e >= a.ne) return;
+    const int64_t s0 = a.start[e];
+    const int n = a.start[e + 1] - a.start[e];
+    double* red = reinterpret_cast<double*>(smem);                 // [NT/64][39]
+    double* bmean = red + (NT / 64) * 3 * NPART;                  // [MAXBINS]
+    unsigned char* p = reinterpret_cast<unsigned char*>(bmean + MAXBINS);
+    if (n == 0) {
+        if (threadIdx.x < 3 * NPART) a.part[(int64_t)e * 3 * NPART + threadIdx.x] = 0.0;
+        return;
+    }
+    if (n <= a.lds_max) {
+        const int M = a.lds_max;
+        SortKey* kp = reinterpret_cast<SortKey*>(p);
+        double* U0 = reinterpret_cast<double*>(kp + M);
+        double* U1 = U0 + M;
+        double* U2 = U1 + M;
+        uint64_t* PID = reinterpret_cast<uint64_t*>(U2 + M);
+        int32_t* ordA = reinterpret_cast<int32_t*>(PID + M);
+        int32_t* ordB = ordA + M;
+        element_body<NT>(a, e, s0, n, U0, U1, U2, PID, kp, ordA, ordB, bmean, red);
+    } else {
+        const int64_t cap = a.cap;
+        SortKey* kp = reinterpret_cast<SortKey*>(a.gkey) + s0;
+        double* U0 = a.gu3 + s0;
+        double* U1 = a.gu3 + cap + s0;
+        double* U2 = a.gu3 + 2 * cap + s0;
+        uint64_t* PID = reinterpret_cast<uint64_t*>(a.gu3 + 3 * cap) + s0;
+        int32_t* ordA = a.gord + s0;
+        int32_t* ordB = a.gord + cap + s0;
+        element_body<NT>(a, e, s0, n, U0, U1, U2, PID, kp, ordA, ordB, bmean, red);
+    }
+}
+
+size_t element_pass_smem(int lds_max)
+{
+    return (size_t)(EP_NT / 64) * 3 * NPART * sizeof(double) + MAXBINS * sizeof(double) +
+           (size_t)lds_max * (sizeof(SortKey) + 4 * sizeof(double) + 2 * sizeof(int32_t));
+}
+
+// =====================================================================================
+// node finalize (Sec. 3.3): fixed-order sum over the elements around the node
+// =====================================================================================
+__global__ void __launch_bounds__(256) k_node_finalize(NodeArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) {
+        a.meta[0] = a.start[a.ne];   // used slots after compaction
+        a.meta[1] = a.start[a.ne];   // live particles
+    }
+    if (i >= a.nn) return;
+    double S[NPART];
+#pragma unroll
+    for (int q = 0; q < NPART; ++q) S[q] = 0.0;
+    for (int64_t j = a.n2e_ptr[i]; j < a.n2e_ptr[i + 1]; ++j) {
+        const double* pp = a.part + (int64_t)a.n2e[j] * NPART;
+#pragma unroll
+        for (int q = 0; q < NPART; ++q) S[q] += pp[q];
+    }
+    double* o = a.stats + i * NSTAT;
+    double* r = a.shift + i * 5;
+    const double W = S[0];
+    o[0] = W;
+    if (W == 0.0) {
+        const double nan = __builtin_nan("");
+        for (int q = 1; q < NSTAT; ++q) o[q] = nan;
+        for (int q = 0; q < 5; ++q) r[q] = 0.0;
+        return;
+    }
+    double d[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) d[q] = S[1 + q] / W;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) o[1 + q] = r[q] + d[q];
+    o[6] = S[6] / W - d[0] * d[0];
+    o[7] = S[7] / W - d[1] * d[1];
+    o[8] = S[8] / W - d[2] * d[2];
+    o[9] = S[9] / W - d[0] * d[1];
+    o[10] = S[10] / W - d[0] * d[2];
+    o[11] = S[11] / W - d[1] * d[2];
+    o[12] = S[12] / W - d[4] * d[4];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) r[q] = o[1 + q];
+}
+
+// =====================================================================================
+// set-up (Sec. 3.7): ppe particles per element
+// =====================================================================================
+__global__ void __launch_bounds__(256) k_init(InitArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    const int32_t e = (int32_t)(i / a.ppe);
+    const ElemGeo* G = a.geo + e;
+    const uint64_t pid = (uint64_t)i;
+    const Words4 wA = rng_draw(a.key, pid, 0, TAG_INIT, 0);
+    const Words4 wB = rng_draw(a.key, pid, 0, TAG_INIT, 1);
+    double s = u01(wA.w0), t = u01(wA.w1);
+    if (s + t > 1.0) {
+        s = 1.0 - s;
+        t = 1.0 - t;
+    }
+    const double x = G->x[0] + s * (G->x[1] - G->x[0]) + t * (G->x[2] - G->x[0]);
+    const double y = G->y[0] + s * (G->y[1] - G->y[0]) + t * (G->y[2] - G->y[0]);
+    double na, nb, nc;
+    area_coords(G, x, y, na, nb, nc);
+    const double la = na / G->area, lb = nb / G->area, lc = nc / G->area;
+    const double* FA = a.node + (int64_t)G->node[0] * NODE_STRIDE;
+    const double* FB = a.node + (int64_t)G->node[1] * NODE_STRIDE;
+    const double* FC = a.node + (int64_t)G->node[2] * NODE_STRIDE;
+    double z0, z1, z2, z3;
+    box_muller(wA.w2, wA.w3, z0, z1);
+    box_muller(wB.w0, wB.w1, z2, z3);
+    const double mu0 = la * FA[NF_MU] + lb * FB[NF_MU] + lc * FC[NF_MU];
+    const double mu1 = la * FA[NF_MU + 1] + lb * FB[NF_MU + 1] + lc * FC[NF_MU + 1];
+    const double mu2 = la * FA[NF_MU + 2] + lb * FB[NF_MU + 2] + lc * FC[NF_MU + 2];
+    const double omm = la * FA[NF_OM] + lb * FB[NF_OM] + lc * FC[NF_OM];
+    a.s.x[i] = x;
+    a.s.y[i] = y;
+    a.s.u0[i] = mu0 + a.u_sigma * z0;
+    a.s.u1[i] = mu1 + a.u_sigma * z1;
+    a.s.u2[i] = mu2 + a.u_sigma * z2;
+    a.s.om[i] = gamma_draw(a.omega_shape, omm, a.key, pid, 0, TAG_INIT_GAMMA);
+    double dx = x - a.src_x, dy = y - a.src_y;
+    if (a.period > 0.0) {
+        if (dx > 0.5 * a.period) dx -= a.period;
+        else if (dx < -0.5 * a.period) dx += a.period;
+    }
+    a.s.psi[i] = (dx * dx + dy * dy < a.src_r2) ? 1.0 : 0.0;
+    a.s.w[i] = 1.0;
+    a.s.pid[i] = pid;
+    a.s.elem[i] = e;
+}
+
+// micromixing timescale per element, Eq. (25) at the centroid
+__global__ void __launch_bounds__(256) k_tm(const ElemGeo* __restrict__ geo, const double* __restrict__ node,
+                                            int64_t ne, ModelC m, double src_x, double src_y, double src_r,
+                                            double period, double* __restrict__ tm)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= ne) return;
+    const ElemGeo* G = geo + e;
+    const double* A = node + (int64_t)G->node[0] * NODE_STRIDE;
+    const double* B = node + (int64_t)G->node[1] * NODE_STRIDE;
+    const double* C = node + (int64_t)G->node[2] * NODE_STRIDE;
+    auto cen = [&](int q) { return (A[q] + B[q] + C[q]) / 3.0; };
+    const double k = 0.5 * (cen(NF_RE) + cen(NF_RE + 1) + cen(NF_RE + 2));
+    const double Om = cen(NF_OM);
+    const double eps = Om * (k + m.nu * m.CT * m.CT * Om);
+    const double m0 = cen(NF_MU), m1 = cen(NF_MU + 1), m2 = cen(NF_MU + 2);
+    const double Uc = sqrt(m0 * m0 + m1 * m1 + m2 * m2);
+    const double cx = (G->x[0] + G->x[1] + G->x[2]) / 3.0, cy = (G->y[0] + G->y[1] + G->y[2]) / 3.0;
+    double dx = cx - src_x, dy = cy - src_y;
+    if (period > 0.0) {
+        if (dx > 0.5 * period) dx -= period;
+        else if (dx < -0.5 * period) dx += period;
+    }
+    const double dist = sqrt(dx * dx + dy * dy);
+    const double first = Uc > 0.0 ? m.Cs * cbrt(src_r * src_r / eps) + m.Ct * dist / Uc : __builtin_inf();
+    const double second = fmax(k / eps, m.CT * sqrt(m.nu / eps));
+    tm[e] = fmin(first, second);
+}
+
+// =====================================================================================
+// number control (Sec. 3.7, App. B)
+// =====================================================================================
+__global__ void __launch_bounds__(256) k_ctl_plan(ControlArgs a)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int merged = 0, empty = 0, below = 0, above = 0;
+    if (e < a.ne) {
+        const int64_t s0 = a.start[e];
+        const int n = a.start[e + 1] - a.start[e];
+        int c = 0;
+        if (n == 0) {
+            empty = 1;
+        } else if (n < a.n_min) {
+            below = 1;
+            c = (a.n_min - n) < n ? (a.n_min - n) : n;
+        } else if (n > a.n_max) {
+            above = 1;
+            int g0, g1, g2;
+            const int Cp = bin_structure(n, a.bins0, a.bins1, a.bins2, a.minpb, g0, g1, g2);
+            const int want = n - a.n_max;
+            for (int j = 0; merged < want; ++j) {
+                bool any = false;
+                for (int b = 0; b < Cp && merged < want; ++b) {
+                    const long long first = ((long long)b * n + Cp - 1) / Cp;
+                    const long long size = ((long long)(b + 1) * n + Cp - 1) / Cp - first;
+                    if (size < 2LL * j + 2) continue;
+                    any = true;
+                    const int64_t r = s0 + first + 2 * j, v = r + 1;
+                    const double wr = a.s.w[r], wv = a.s.w[v];
+                    const double W = wr + wv;
+                    a.s.u0[r] = (wr * a.s.u0[r] + wv * a.s.u0[v]) / W;
+                    a.s.u1[r] = (wr * a.s.u1[r] + wv * a.s.u1[v]) / W;
+                    a.s.u2[r] = (wr * a.s.u2[r] + wv * a.s.u2[v]) / W;
+                    a.s.om[r] = (wr * a.s.om[r] + wv * a.s.om[v]) / W;
+                    a.s.psi[r] = (wr * a.s.psi[r] + wv * a.s.psi[v]) / W;
+                    a.s.w[r] = W;
+                    a.s.elem[v] = -1;
+                    ++merged;
+                }
+                if (!any) break;
+            }
+        }
+        a.clone[e] = c;
+    }
+    const int sm = wave_sum_int(merged), se = wave_sum_int(empty), sb = wave_sum_int(below),
+              sa = wave_sum_int(above);
+    if (lane_id() == 0) {
+        if (sm) atomicAdd(a.rep + 0, (unsigned long long)sm);
+        if (se) atomicAdd(a.rep + 1, (unsigned long long)se);
+        if (sb) atomicAdd(a.rep + 2, (unsigned long long)sb);
+        if (sa) atomicAdd(a.rep + 3, (unsigned long long)sa);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_ctl_apply(ControlArgs a)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= a.ne) return;
+    const int c = a.clone[e];
+    if (c == 0) return;
+    const int64_t s0 = a.start[e];
+    const int64_t n = a.start[e + 1] - a.start[e];
+    const int64_t base = *a.nslots + a.off[e];
+    for (int i = 0; i < c; ++i) {
+        const int64_t src = s0 + ((2LL * i + 1) * n) / (2LL * c);
+        const int64_t dst = base + i;
+        if (dst >= a.cap) {
+            atomicOr(a.err, ERR_CAPACITY);
+            continue;
+        }
+        const double w = 0.5 * a.s.w[src];
+        a.s.w[src] = w;
+        a.s.x[dst] = a.s.x[src];
+        a.s.y[dst] = a.s.y[src];
+        a.s.u0[dst] = a.s.u0[src];
+        a.s.u1[dst] = a.s.u1[src];
+        a.s.u2[dst] = a.s.u2[src];
+        a.s.om[dst] = a.s.om[src];
+        a.s.psi[dst] = a.s.psi[src];
+        a.s.w[dst] = w;
+        a.s.pid[dst] = a.next_pid + (uint64_t)(a.off[e] + i);
+        a.s.elem[dst] = (int32_t)e;
+    }
+}
+
+// slots and live count after control; the device report gets the clone total
+__global__ void k_ctl_finish(int64_t* __restrict__ meta, const int32_t* __restrict__ off, int64_t ne,
+                             const unsigned long long* __restrict__ rep, int64_t cap)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t total = off[ne];
+    int64_t slots = meta[0] + total;
+    meta[0] = slots > cap ? cap : slots;
+    meta[1] = meta[1] - (int64_t)rep[0] + total;
+    meta[2] = total;
+}
+
+__global__ void __launch_bounds__(256) k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* __restrict__ p, int64_t n,
+                                                  unsigned long long v)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_fill_f64(double* __restrict__ p, int64_t n, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// initial shift of the single-pass moments: the frozen <U>, <omega> and psi = 0
+__global__ void __launch_bounds__(256) k_shift_init(const double* __restrict__ node, int64_t nn,
+                                                    double* __restrict__ shift)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nn) return;
+    const double* F = node + i * NODE_STRIDE;
+    shift[i * 5 + 0] = F[NF_MU];
+    shift[i * 5 + 1] = F[NF_MU + 1];
+    shift[i * 5 + 2] = F[NF_MU + 2];
+    shift[i * 5 + 3] = F[NF_OM];
+    shift[i * 5 + 4] = 0.0;
+}
+
+// =====================================================================================
+// launchers
+// =====================================================================================
+static inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) / nt); }
+
+void launch_advance(const AdvanceArgs& a, int64_t n_ub, hipStream_t s)
+{
+    if (n_ub > 0) hipLaunchKernelGGL(k_advance, dim3(blocks_for(n_ub, 256)), dim3(256), 0, s, a);
+}
+void launch_count(const int32_t* elem, const int64_t* nslots, int64_t n_ub, int64_t ne, int32_t* counts,
+                  uint32_t* err, hipStream_t s)
+{
+    if (n_ub > 0) hipLaunchKernelGGL(k_count, dim3(blocks_for(n_ub, 256)), dim3(256), 0, s, elem, nslots, ne, counts, err);
+}
+int64_t scan_blocks(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE; }
+void launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* tmp, hipStream_t s)
+{
+    const int64_t nb = scan_blocks(n);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_NT), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_NT), 0, s, tmp, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_NT), 0, s, in, n, tmp, out, nb);
+}
+int64_t scan_max_elems() { return (int64_t)SCAN_TILE * SCAN_TILE; }
+void launch_scatter(const int32_t* elem, const int64_t* nslots, int64_t n_ub, int64_t ne, int32_t* counts,
+                    const int32_t* start, int32_t* idx, uint32_t* err, hipStream_t s)
+{
+    if (n_ub > 0)
+        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n_ub, 256)), dim3(256), 0, s, elem, nslots, ne, counts, start, idx, err);
+}
+hipError_t prepare_element_pass(int lds_max)
+{
+    return hipFuncSetAttribute((const void*)k_element_pass<EP_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)element_pass_smem(lds_max));
+}
+void launch_element_pass(const ElementArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_element_pass<EP_NT>, dim3((unsigned)a.ne), dim3(EP_NT), element_pass_smem(a.lds_max), s, a);
+}
+void launch_node_finalize(const NodeArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_node_finalize, dim3(blocks_for(a.nn > 0 ? a.nn : 1, 256)), dim3(256), 0, s, a);
+}
+void launch_init(const InitArgs& a, hipStream_t s)
+{
+    if (a.n > 0) hipLaunchKernelGGL(k_init, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, a);
+}
+void launch_tm(const ElemGeo* geo, const double* node, int64_t ne, ModelC m, double sx, double sy, double sr,
+               double period, double* tm, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tm, dim3(blocks_for(ne, 256)), dim3(256), 0, s, geo, node, ne, m, sx, sy, sr, period, tm);
+}
+void launch_ctl_plan(const ControlArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_plan, dim3(blocks_for(a.ne, 256)), dim3(256), 0, s, a);
+}
+void launch_ctl_apply(const ControlArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_apply, dim3(blocks_for(a.ne, 256)), dim3(256), 0, s, a);
+}
+void launch_ctl_finish(int64_t* meta, const int32_t* off, int64_t ne, const unsigned long long* rep, int64_t cap,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_finish, dim3(1), dim3(64), 0, s, meta, off, ne, rep, cap);
+}
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+}
+void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+}
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+}
+void launch_shift_init(const double* node, int64_t nn, double* shift, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_shift_init, dim3(blocks_for(nn, 256)), dim3(256), 0, s, node, nn, shift);
+}
+
+}  // namespace pdfgpu

@@ -1,0 +1,244 @@
+"""ctypes binding of libpdfgpu.so (declared in include/pdf.h).
+
+Argument marshalling only: every step of the particle time step runs in the HIP
+kernels of the library.  The library must have been built (``__graft_entry__.build()``
+or ``python paper_1006_0532_amd/build.py``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdfgpu.so")
+
+PDF_NSTAT = 13
+PDF_NCOUNTERS = 8
+PDF_NTIMERS = 12
+TIMER_NAMES = ["init", "advance", "scan", "scatter", "element_pass", "node_finalize",
+               "control_plan", "control_scan", "control_apply", "fill", "count", "other"]
+COUNTER_NAMES = ["wall_a", "wall_b", "reflections", "fallbacks", "omega_reflections",
+                 "c0_clamps", "walk_steps", "source_hits"]
+STATUS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "HIP", -4: "MESH", -5: "CAPACITY", -6: "LOST",
+          -7: "NONFINITE", -8: "STATE"}
+
+# every symbol include/pdf.h declares
+EXPORTS = ["pdf_grid_create", "pdf_grid_destroy", "pdf_particles_init", "pdf_ens_destroy", "pdf_step",
+           "pdf_stats", "pdf_control", "pdf_count", "pdf_particles_export", "pdf_particles_import",
+           "pdf_counters", "pdf_timing", "pdf_sync", "pdf_last_error"]
+
+
+class PdfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("xy", C.POINTER(C.c_double)), ("n_elems", C.c_int64),
+                ("tri", C.POINTER(C.c_int32)), ("edge_kind", C.POINTER(C.c_uint8)),
+                ("period_x", C.c_double)]
+
+
+class FieldsDesc(C.Structure):
+    _fields_ = [(n, C.POINTER(C.c_double)) for n in ("grad_p", "wp", "mean_u", "mean_omega", "rey")]
+
+
+class Model(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("nu", "rho", "C3", "C4", "CT", "Cw1", "Cw2", "Cs", "Ct")]
+
+
+class InitDesc(C.Structure):
+    _fields_ = [("ppe", C.c_int32), ("u_sigma", C.c_double), ("omega_shape", C.c_double),
+                ("src_x", C.c_double), ("src_y", C.c_double), ("src_r", C.c_double),
+                ("src_continuous", C.c_int32), ("bins", C.c_int32 * 3), ("min_per_bin", C.c_int32),
+                ("precision", C.c_int32), ("seed", C.c_uint64), ("capacity", C.c_int64)]
+
+
+class ControlReport(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("live", "cloned", "merged", "empty", "below", "above")]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (no fallback of any kind)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libpdfgpu.so not built at {path}; run __graft_entry__.build()")
+    L = C.CDLL(path)
+    vp, dp, ip, u8p, u64p, i64p = (C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_uint8), C.POINTER(C.c_uint64), C.POINTER(C.c_int64))
+    sig = {
+        "pdf_grid_create": [C.POINTER(MeshDesc), C.POINTER(FieldsDesc), C.POINTER(Model), vp, C.POINTER(vp)],
+        "pdf_grid_destroy": [vp],
+        "pdf_particles_init": [C.POINTER(vp), C.POINTER(InitDesc), C.c_int32, vp, C.POINTER(vp)],
+        "pdf_ens_destroy": [vp],
+        "pdf_step": [vp, dp, C.c_int32, vp],
+        "pdf_stats": [vp, C.c_int32, vp, C.c_int32, vp],
+        "pdf_control": [vp, C.c_int32, C.c_int32, C.POINTER(ControlReport), vp],
+        "pdf_count": [vp, C.c_int32, i64p],
+        "pdf_particles_export": [vp, C.c_int32, C.c_int64, dp, dp, dp, dp, dp, dp, u64p, ip, i64p, vp],
+        "pdf_particles_import": [vp, C.c_int32, C.c_int64, dp, dp, dp, dp, dp, dp, u64p, ip, C.c_int64,
+                                 C.c_uint64, vp],
+        "pdf_counters": [vp, C.c_int32, i64p],
+        "pdf_timing": [vp, C.c_int32, dp, i64p],
+        "pdf_sync": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int32
+    L.pdf_last_error.argtypes = []
+    L.pdf_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != 0:
+        raise PdfError(st, load().pdf_last_error().decode())
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def current_stream() -> int:
+    """Handle of torch's current HIP stream (0 = default stream when torch is absent)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return 0
+
+
+class Grid:
+    def __init__(self, mesh, fields, model: dict, stream: int | None = None):
+        L = load()
+        self._xy = np.ascontiguousarray(mesh.xy, np.float64)
+        self._tri = np.ascontiguousarray(mesh.tri, np.int32)
+        self._kind = np.ascontiguousarray(mesh.edge_kind, np.uint8)
+        self._f = [np.ascontiguousarray(a, np.float64) for a in fields.as_tuple()]
+        md = MeshDesc(mesh.n_nodes, _ptr(self._xy, C.c_double), mesh.n_elems, _ptr(self._tri, C.c_int32),
+                      _ptr(self._kind, C.c_uint8), float(mesh.period_x))
+        fd = FieldsDesc(*[_ptr(a, C.c_double) for a in self._f])
+        mo = Model(**{n: float(model[n]) for n, _ in Model._fields_})
+        h = C.c_void_p()
+        _check(L.pdf_grid_create(C.byref(md), C.byref(fd), C.byref(mo),
+                                 C.c_void_p(current_stream() if stream is None else stream), C.byref(h)))
+        self.h = h
+        self.nn, self.ne = mesh.n_nodes, mesh.n_elems
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            load().pdf_grid_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_init(d: dict, capacity: int = 0, precision: int = 0) -> InitDesc:
+    s = InitDesc()
+    s.ppe = int(d["ppe"]); s.u_sigma = float(d["u_sigma"]); s.omega_shape = float(d["omega_shape"])
+    s.src_x, s.src_y, s.src_r = float(d["src_x"]), float(d["src_y"]), float(d["src_r"])
+    s.src_continuous = int(d["src_continuous"])
+    for i in range(3):
+        s.bins[i] = int(d["bins"][i])
+    s.min_per_bin = int(d["min_per_bin"]); s.precision = int(precision); s.seed = int(d["seed"])
+    s.capacity = int(capacity or d.get("capacity", 0))
+    return s
+
+
+class Ensemble:
+    def __init__(self, grid: Grid, init: dict, capacity: int = 0, stream: int | None = None):
+        L = load()
+        self.grid = grid
+        self.desc = make_init(init, capacity)
+        grids = (C.c_void_p * 1)(grid.h.value)
+        h = C.c_void_p()
+        self.stream = current_stream() if stream is None else stream
+        _check(L.pdf_particles_init(grids, C.byref(self.desc), 1, C.c_void_p(self.stream), C.byref(h)))
+        self.h = h
+
+    def step(self, dt: float, n: int = 1):
+        d = (C.c_double * 1)(float(dt))
+        _check(load().pdf_step(self.h, d, int(n), C.c_void_p(self.stream)))
+
+    def sync(self):
+        _check(load().pdf_sync(self.h))
+
+    def stats(self) -> np.ndarray:
+        out = np.empty((self.grid.nn, PDF_NSTAT))
+        _check(load().pdf_stats(self.h, 0, out.ctypes.data_as(C.c_void_p), 0, C.c_void_p(self.stream)))
+        return out
+
+    def stats_device(self, ptr: int):
+        _check(load().pdf_stats(self.h, 0, C.c_void_p(ptr), 1, C.c_void_p(self.stream)))
+
+    def control(self, n_min: int, n_max: int) -> dict:
+        r = ControlReport()
+        _check(load().pdf_control(self.h, int(n_min), int(n_max), C.byref(r), C.c_void_p(self.stream)))
+        return {n: getattr(r, n) for n, _ in ControlReport._fields_}
+
+    def count(self) -> int:
+        v = C.c_int64()
+        _check(load().pdf_count(self.h, 0, C.byref(v)))
+        return int(v.value)
+
+    def export(self, sort_by_pid: bool = True) -> dict:
+        n = self.count()
+        o = dict(x=np.empty(n), y=np.empty(n), u=np.empty((n, 3)), om=np.empty(n), psi=np.empty(n),
+                 w=np.empty(n), pid=np.empty(n, np.uint64), elem=np.empty(n, np.int32))
+        got = C.c_int64()
+        _check(load().pdf_particles_export(self.h, 0, n, *[_ptr(o[k], C.c_double) for k in
+                                                           ("x", "y", "u", "om", "psi", "w")],
+                                           _ptr(o["pid"], C.c_uint64), _ptr(o["elem"], C.c_int32),
+                                           C.byref(got), C.c_void_p(self.stream)))
+        assert got.value == n
+        if sort_by_pid:
+            order = np.argsort(o["pid"], kind="stable")
+            o = {k: v[order] for k, v in o.items()}
+        return o
+
+    def import_state(self, st: dict, step: int, next_pid: int):
+        n = len(st["x"])
+        arrs = [np.ascontiguousarray(st[k], np.float64) for k in ("x", "y", "u", "om", "psi", "w")]
+        pid = np.ascontiguousarray(st["pid"], np.uint64)
+        el = np.ascontiguousarray(st["elem"], np.int32)
+        _check(load().pdf_particles_import(self.h, 0, n, *[_ptr(a, C.c_double) for a in arrs],
+                                           _ptr(pid, C.c_uint64), _ptr(el, C.c_int32), int(step),
+                                           int(next_pid), C.c_void_p(self.stream)))
+
+    def counters(self) -> dict:
+        o = (C.c_int64 * PDF_NCOUNTERS)()
+        _check(load().pdf_counters(self.h, 0, o))
+        return dict(zip(COUNTER_NAMES, o[:]))
+
+    def timing(self, enable: bool):
+        ms = (C.c_double * PDF_NTIMERS)()
+        cnt = (C.c_int64 * PDF_NTIMERS)()
+        _check(load().pdf_timing(self.h, int(enable), ms, cnt))
+        return {TIMER_NAMES[i]: (ms[i], cnt[i]) for i in range(PDF_NTIMERS)}
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            load().pdf_ens_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle on the same seeded
+inputs, element by element and node by node."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1006_0532_amd import workloads as W
+from tests.common import box
+from tests.parity import compare_states, compare_stats
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "a GPU is required"
+    from paper_1006_0532_amd import pdfgpu
+    pdfgpu.load()
+    return pdfgpu
+
+
+def _pair(gpu, mesh, fields, model, init, capacity=0):
+    og = O.Grid(mesh, fields, model)
+    oe = O.Ensemble(og, init)
+    gg = gpu.Grid(mesh, fields, model)
+    ge = gpu.Ensemble(gg, init, capacity=capacity)
+    return og, oe, gg, ge
+
+
+def _skip_nodes(mesh, excl):
+    return set(mesh.tri[list(excl)].ravel().tolist()) if excl else set()
+
+
+def _length(mesh):
+    return mesh.period_x if mesh.period_x > 0 else float(np.ptp(mesh.xy[:, 0]))
+
+
+def test_init_parity(gpu):
+    _say("test_init_parity: channel_small")
+    mesh, f, mo, ini = W.channel_small()
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    g, r = ge.export(), oe.export()
+    assert np.array_equal(g["elem"], r["elem"])
+    compare_states(g, r, frame, _length(mesh))
+    compare_stats(ge.stats(), oe.stats())
+
+
+@pytest.mark.parametrize("steps", [1, 20])
+def test_channel_small_step_parity(gpu, steps):
+    """Full step (advance, track, group, bin, mix, statistics) every step, 2e5 particles."""
+    _say(f"test_channel_small_step_parity: {steps} steps")
+    mesh, f, mo, ini = W.channel_small()
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    excl = set()
+    for n in range(steps):
+        oe.step(1e-3)
+        ge.step(1e-3)
+        rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+        compare_stats(ge.stats(), oe.stats(), _skip_nodes(mesh, excl))
+    assert len(excl) <= 4
+    assert ge.counters() == oe.counters()
+
+
+def test_control_parity(gpu):
+    """Number control after a few steps: splits and same-bin merges match the oracle."""
+    _say("test_control_parity")
+    mesh = W.channel_mesh(20, 24, stretch=1.1 ** 8, seed=21)
+    f = W.channel_fields(mesh)
+    mo = W.model_constants()
+    ini = W.init_desc(ppe=40, bins=(4, 2, 2), src_x=3.0, src_r=0.4)
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    excl = set()
+    for n in range(4):
+        oe.step(2e-3)
+        ge.step(2e-3)
+        ro = oe.control(38, 42)
+        rg = ge.control(38, 42)
+        assert ro == {k: rg[k] for k in ro}, (ro, rg)
+        assert rg["cloned"] > 0 and rg["merged"] > 0
+        rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+    oe.step(2e-3)
+    ge.step(2e-3)
+    compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+    compare_stats(ge.stats(), oe.stats(), _skip_nodes(mesh, excl))
+
+
+def test_walls_slip_and_multistep_walks(gpu):
+    """Tiny jittered box with large steps: multi-element walks, free-slip reflections,
+    periodic seam; element ids must equal the oracle's."""
+    _say("test_walls_slip_and_multistep_walks")
+    mesh = box(5, 4, length=2.5, jitter=0.2, seed=5)
+    f = W.uniform_fields(mesh, mean_u=(1.0, 0.5, 0.0), mean_omega=3.0)
+    mo = W.model_constants(nu=1e-3)
+    ini = W.init_desc(ppe=200, u_sigma=0.4, src_x=1.0, src_r=0.3, bins=(3, 2, 1))
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    excl = set()
+    for n in range(5):
+        oe.step(0.05)
+        ge.step(0.05)
+        rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+    c = ge.counters()
+    assert c["reflections"] > 0 and c["walk_steps"] > 0
+    assert c == oe.counters()
+
+
+def test_no_slip_events(gpu):
+    """Near-wall particles: trajectories (a) and (b) with Gamma frequency resampling."""
+    _say("test_no_slip_events")
+    mesh = W.channel_mesh(12, 16, length=2.0, stretch=1.1 ** 7, seed=8)
+    f = W.channel_fields(mesh)
+    mo = W.model_constants(nu=5e-4)
+    ini = W.init_desc(ppe=60, src_r=0.0)
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    excl = set()
+    for n in range(6):
+        oe.step(2e-3)
+        ge.step(2e-3)
+        rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+    c = ge.counters()
+    assert c["wall_a"] > 0 and c["wall_b"] > 0
+    assert c == oe.counters()
+
+
+def test_large_elements_use_global_scratch(gpu):
+    """Elements above the on-chip limit take the global-memory path of the element pass."""
+    _say("test_large_elements_use_global_scratch")
+    mesh = box(2, 2, length=2.0, jitter=0.0)
+    f = W.uniform_fields(mesh, mean_u=(0.2, 0.0, 0.0))
+    mo = W.model_constants()
+    ini = W.init_desc(ppe=2500, bins=(5, 5, 5), src_x=1.0, src_r=0.5)
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    for n in range(2):
+        oe.step(1e-3)
+        ge.step(1e-3)
+        compare_states(ge.export(), oe.export(), frame, _length(mesh))
+    compare_stats(ge.stats(), oe.stats())
+
+
+def test_determinism_and_resume(gpu):
+    """Bitwise-identical reruns; 6 steps == 3 + export/import + 3."""
+    _say("test_determinism_and_resume")
+    mesh, f, mo, ini = W.channel_small(nx=16, ny=20)
+    gg = gpu.Grid(mesh, f, mo)
+    a = gpu.Ensemble(gg, ini)
+    a.step(1e-3, 6)
+    b = gpu.Ensemble(gg, ini)
+    b.step(1e-3, 6)
+    sa, sb = a.export(), b.export()
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    assert np.array_equal(a.stats(), b.stats(), equal_nan=True)
+    c = gpu.Ensemble(gg, ini)
+    c.step(1e-3, 3)
+    snap = c.export()
+    d = gpu.Ensemble(gg, ini)
+    d.import_state(snap, step=3, next_pid=len(snap["x"]))
+    d.step(1e-3, 3)
+    sd = d.export()
+    for k in sa:
+        assert np.array_equal(sa[k], sd[k]), k
+
+
+def test_error_paths(gpu):
+    """A particle outside the domain is reported as lost; bad arguments are rejected."""
+    _say("test_error_paths")
+    mesh, f, mo, ini = W.channel_small(nx=8, ny=10)
+    gg = gpu.Grid(mesh, f, mo)
+    e = gpu.Ensemble(gg, ini)
+    st = e.export()
+    st["y"][0] = 50.0          # far outside the channel: more than four reflections needed
+    e.import_state(st, step=0, next_pid=len(st["x"]))
+    e.step(1e-3)
+    with pytest.raises(gpu.PdfError) as ex:
+        e.sync()
+    assert ex.value.status == -6
+    e2 = gpu.Ensemble(gg, ini)
+    with pytest.raises(gpu.PdfError):
+        e2.control(10, 5)
+    with pytest.raises(gpu.PdfError):
+        e2.step(-1.0)
+    bad = W.Mesh(mesh.xy, mesh.tri[:, ::-1].copy(), mesh.edge_kind, mesh.period_x)
+    with pytest.raises(gpu.PdfError) as ex:
+        gpu.Grid(bad, f, mo)
+    assert ex.value.status == -4
