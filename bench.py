@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--ppe", type=int, default=200)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--copy-calib", action="store_true",
+                   help="run one 1 GiB device copy first (known-size kernel for HBM counter scaling)")
     return p.parse_args()
 
 
@@ -85,6 +87,13 @@ def main():
     from paper_1006_0532_amd import pdfgpu, workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calib:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        s = a.sum()          # reads 1 GiB: fetch-side reference
+        torch.cuda.synchronize()
+        del a, b, s
     dt, ctl = 2.0e-4, (150, 250)
     t_setup = time.perf_counter()
     mesh = W.channel_mesh(args.nx, args.ny)

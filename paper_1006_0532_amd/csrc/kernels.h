@@ -6,6 +6,7 @@ namespace pdfgpu {
 
 constexpr int EP_NT = 256;      // threads per element in the element pass
 constexpr int MAXBINS = 1024;   // upper bound of bins[0]*bins[1]*bins[2]
+constexpr int EP_BIG_BLOCKS = 512;  // workgroups of the large-element pass
 
 struct AdvanceArgs {
     Soa s;
@@ -40,6 +41,9 @@ struct ElementArgs {
     int64_t cap;
     int32_t bins0, bins1, bins2, minpb;
     int32_t lds_max;
+    int32_t ppl;          // particles per lane of the wavefront kernel (1..6, 8)
+    int32_t* big_list;    // [ne] elements left to the workgroup kernel
+    int32_t* big_count;
     double* gkey;
     int32_t* gord;
     double* gu3;
@@ -55,6 +59,7 @@ struct NodeArgs {
     const int32_t* start;
     int64_t ne;
     int64_t* meta;
+    int32_t* big_count;
 };
 
 struct InitArgs {

@@ -253,27 +253,29 @@ __global__ void __launch_bounds__(256) k_advance(AdvanceArgs a)
     wave_runs(key, leader, len, rank);
     if (rank == 0 && key >= 0) atomicAdd(a.counts + key, len);
 
-    // event counters
-    const int lane = lane_id();
-    const int c_a = __popcll(__ballot(ev_a != 0)), c_b = __popcll(__ballot(ev_b != 0));
-    const int c_o = __popcll(__ballot(omrefl != 0)), c_c = __popcll(__ballot(clamp != 0));
-    const int c_s = __popcll(__ballot(src != 0));
-    const unsigned long long anymove = __ballot(steps != 0 || refl != 0 || fb != 0);
-    int s_steps = 0, s_refl = 0, s_fb = 0;
-    if (anymove) {
-        s_steps = wave_sum_int(steps);
-        s_refl = wave_sum_int(refl);
-        s_fb = wave_sum_int(fb);
+    // event counters: wavefront sums, then one workgroup sum per counter added to one of
+    // CNT_SLOTS spread copies (no single hot address)
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    __shared__ int wsum[4][NCOUNT];
+    int v[NCOUNT];
+    v[0] = __popcll(__ballot(ev_a != 0));
+    v[1] = __popcll(__ballot(ev_b != 0));
+    v[4] = __popcll(__ballot(omrefl != 0));
+    v[5] = __popcll(__ballot(clamp != 0));
+    v[7] = __popcll(__ballot(src != 0));
+    v[2] = v[3] = v[6] = 0;
+    if (__ballot(steps != 0 || refl != 0 || fb != 0)) {
+        v[6] = wave_sum_int(steps);
+        v[2] = wave_sum_int(refl);
+        v[3] = wave_sum_int(fb);
     }
-    if (lane == 0) {
-        if (c_a) atomicAdd(a.cnt + 0, (unsigned long long)c_a);
-        if (c_b) atomicAdd(a.cnt + 1, (unsigned long long)c_b);
-        if (s_refl) atomicAdd(a.cnt + 2, (unsigned long long)s_refl);
-        if (s_fb) atomicAdd(a.cnt + 3, (unsigned long long)s_fb);
-        if (c_o) atomicAdd(a.cnt + 4, (unsigned long long)c_o);
-        if (c_c) atomicAdd(a.cnt + 5, (unsigned long long)c_c);
-        if (s_steps) atomicAdd(a.cnt + 6, (unsigned long long)s_steps);
-        if (c_s) atomicAdd(a.cnt + 7, (unsigned long long)c_s);
+    if (lane == 0)
+        for (int q = 0; q < NCOUNT; ++q) wsum[wid][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x < NCOUNT) {
+        const int q = threadIdx.x;
+        const int tot = wsum[0][q] + wsum[1][q] + wsum[2][q] + wsum[3][q];
+        if (tot) atomicAdd(a.cnt + q * CNT_SLOTS + (blockIdx.x & (CNT_SLOTS - 1)), (unsigned long long)tot);
     }
 }
 
@@ -585,41 +587,283 @@ __device__ __forceinline__ void element_body(const ElementArgs& a, int32_t e, in
     }
 }
 
+// Elements with more particles than the wavefront kernel holds: one workgroup per element,
+// taken from the worklist the wavefront kernel fills (on-chip keys up to lds_max
+// particles, global scratch at the element's segment offset above that).
 template <int NT>
-__global__ void __launch_bounds__(NT) k_element_pass(ElementArgs a)
+__global__ void __launch_bounds__(NT) k_element_block(ElementArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    const int32_t e = (int32_t)blockIdx.x;
-    if (e >= a.ne) return;
-    const int64_t s0 = a.start[e];
-    const int n = a.start[e + 1] - a.start[e];
     double* red = reinterpret_cast<double*>(smem);                 // [NT/64][39]
     double* bmean = red + (NT / 64) * 3 * NPART;                  // [MAXBINS]
     unsigned char* p = reinterpret_cast<unsigned char*>(bmean + MAXBINS);
+    const int nbig = *a.big_count;
+    for (int k = blockIdx.x; k < nbig; k += gridDim.x) {
+        const int32_t e = a.big_list[k];
+        const int64_t s0 = a.start[e];
+        const int n = a.start[e + 1] - a.start[e];
+        if (n <= a.lds_max) {
+            const int M = a.lds_max;
+            SortKey* kp = reinterpret_cast<SortKey*>(p);
+            double* U0 = reinterpret_cast<double*>(kp + M);
+            double* U1 = U0 + M;
+            double* U2 = U1 + M;
+            uint64_t* PID = reinterpret_cast<uint64_t*>(U2 + M);
+            int32_t* ordA = reinterpret_cast<int32_t*>(PID + M);
+            int32_t* ordB = ordA + M;
+            element_body<NT>(a, e, s0, n, U0, U1, U2, PID, kp, ordA, ordB, bmean, red);
+        } else {
+            const int64_t cap = a.cap;
+            SortKey* kp = reinterpret_cast<SortKey*>(a.gkey) + s0;
+            double* U0 = a.gu3 + s0;
+            double* U1 = a.gu3 + cap + s0;
+            double* U2 = a.gu3 + 2 * cap + s0;
+            uint64_t* PID = reinterpret_cast<uint64_t*>(a.gu3 + 3 * cap) + s0;
+            int32_t* ordA = a.gord + s0;
+            int32_t* ordB = a.gord + cap + s0;
+            element_body<NT>(a, e, s0, n, U0, U1, U2, PID, kp, ordA, ordB, bmean, red);
+        }
+        __syncthreads();
+    }
+}
+
+// orders LDS traffic between the lanes of one wavefront
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// wavefronts per workgroup of the wavefront element kernel (LDS stays within 64 KiB)
+template <int PPL>
+struct WaveBlock {
+    static constexpr int waves = PPL >= 6 ? 2 : 4;
+};
+
+// One wavefront per element (up to 64*PPL particles, PPL per lane).  Lanes own particles
+// in load order while the three sort levels rank (U_l, pid) keys staged in LDS; then each
+// lane takes the particles at canonical positions lane + 64 r, so bin sums, partial sums
+// and the coalesced write-out follow the canonical order only.
+template <int PPL>
+__global__ void __launch_bounds__(256) k_element_wave(ElementArgs a)
+{
+    constexpr int N = 64 * PPL;
+    constexpr int RED = 13 * 65 * 8;                      // transposed reduction, padded rows
+    constexpr int R1 = (24 * N > RED) ? 24 * N : RED;     // keys / (w psi, w) / reduction
+    constexpr int WAVE_BYTES = R1 + 4 * N + 8 * N;
+    constexpr int WPB = WaveBlock<PPL>::waves;
+    __shared__ __attribute__((aligned(16))) unsigned char sm[WPB * WAVE_BYTES];
+    // wave-uniform values go through readfirstlane so that they live in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t e = (int64_t)blockIdx.x * WPB + wave;
+    if (e >= a.ne) return;
+    unsigned char* base = sm + wave * WAVE_BYTES;
+    uint64_t* kk = reinterpret_cast<uint64_t*>(base);          // [N] keys by position
+    uint64_t* kpid = kk + N;                                     // [N] pids by position
+    uint64_t* claim = kpid + N;                                  // [N] rank collision check
+    double* wacc = reinterpret_cast<double*>(base);
+    double* red = reinterpret_cast<double*>(base);
+    int32_t* ord = reinterpret_cast<int32_t*>(base + R1);
+    double* bmean = reinterpret_cast<double*>(base + R1 + 4 * N);
+    const int64_t s0 = __builtin_amdgcn_readfirstlane(a.start[e]);
+    const int n = __builtin_amdgcn_readfirstlane(a.start[e + 1]) - (int)s0;
     if (n == 0) {
-        if (threadIdx.x < 3 * NPART) a.part[(int64_t)e * 3 * NPART + threadIdx.x] = 0.0;
+        if (lane < 3 * NPART) a.part[e * 3 * NPART + lane] = 0.0;
         return;
     }
-    if (n <= a.lds_max) {
-        const int M = a.lds_max;
-        SortKey* kp = reinterpret_cast<SortKey*>(p);
-        double* U0 = reinterpret_cast<double*>(kp + M);
-        double* U1 = U0 + M;
-        double* U2 = U1 + M;
-        uint64_t* PID = reinterpret_cast<uint64_t*>(U2 + M);
-        int32_t* ordA = reinterpret_cast<int32_t*>(PID + M);
-        int32_t* ordB = ordA + M;
-        element_body<NT>(a, e, s0, n, U0, U1, U2, PID, kp, ordA, ordB, bmean, red);
-    } else {
-        const int64_t cap = a.cap;
-        SortKey* kp = reinterpret_cast<SortKey*>(a.gkey) + s0;
-        double* U0 = a.gu3 + s0;
-        double* U1 = a.gu3 + cap + s0;
-        double* U2 = a.gu3 + 2 * cap + s0;
-        uint64_t* PID = reinterpret_cast<uint64_t*>(a.gu3 + 3 * cap) + s0;
-        int32_t* ordA = a.gord + s0;
-        int32_t* ordB = a.gord + cap + s0;
-        element_body<NT>(a, e, s0, n, U0, U1, U2, PID, kp, ordA, ordB, bmean, red);
+    if (n > N) {
+        if (lane == 0) {
+            const int k = atomicAdd(a.big_count, 1);
+            a.big_list[k] = (int32_t)e;
+        }
+        return;
+    }
+    // load order: particle j = lane + 64 r
+    int gi[PPL], pos[PPL];
+    double U0[PPL], U1[PPL], U2[PPL];
+    uint64_t pd[PPL];
+#pragma unroll
+    for (int r = 0; r < PPL; ++r) {
+        const int j = lane + 64 * r;
+        pos[r] = j;
+        gi[r] = 0;
+        U0[r] = U1[r] = U2[r] = 0.0;
+        pd[r] = 0;
+        if (j < n) {
+            gi[r] = a.idx[s0 + j];
+            U0[r] = a.in.u0[gi[r]];
+            U1[r] = a.in.u1[gi[r]];
+            U2[r] = a.in.u2[gi[r]];
+            pd[r] = a.in.pid[gi[r]];
+        }
+    }
+    int g0, g1, g2;
+    const int Cp = bin_structure(n, a.bins0, a.bins1, a.bins2, a.minpb, g0, g1, g2);
+    const int gl[3] = {g0, g1, g2};
+    long long C = 1;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        uint64_t mk[PPL];
+        int lo[PPL], hi[PPL];
+#pragma unroll
+        for (int r = 0; r < PPL; ++r) {
+            mk[r] = order_bits(l == 0 ? U0[r] : (l == 1 ? U1[r] : U2[r]));
+            const long long t = C * pos[r] / n;
+            lo[r] = (int)((t * n + C - 1) / C);
+            hi[r] = (int)(((t + 1) * n + C - 1) / C);
+            if (lane + 64 * r < n) {
+                kk[pos[r]] = mk[r];
+                kpid[pos[r]] = pd[r];
+            }
+        }
+        wave_sync();
+        // rank inside the group by the velocity key alone (ties are rare)
+        int rk[PPL];
+#pragma unroll
+        for (int r = 0; r < PPL; ++r) rk[r] = 0;
+        if (l == 0) {
+            for (int q = 0; q < n; ++q) {
+                const uint64_t kq = kk[q];
+#pragma unroll
+                for (int r = 0; r < PPL; ++r) rk[r] += kq < mk[r] ? 1 : 0;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < PPL; ++r)
+                if (lane + 64 * r < n)
+                    for (int q = lo[r]; q < hi[r]; ++q) rk[r] += kk[q] < mk[r] ? 1 : 0;
+        }
+        // equal keys give equal ranks: detect by claiming the slots, then rank exactly
+        // by (key, pid) in that case
+#pragma unroll
+        for (int r = 0; r < PPL; ++r)
+            if (lane + 64 * r < n) claim[lo[r] + (rk[r] < hi[r] - lo[r] ? rk[r] : hi[r] - lo[r] - 1)] = pd[r];
+        wave_sync();
+        bool clash = false;
+#pragma unroll
+        for (int r = 0; r < PPL; ++r)
+            if (lane + 64 * r < n) clash |= claim[lo[r] + (rk[r] < hi[r] - lo[r] ? rk[r] : hi[r] - lo[r] - 1)] != pd[r];
+        if (__ballot(clash)) {
+#pragma unroll
+            for (int r = 0; r < PPL; ++r) {
+                rk[r] = 0;
+                if (lane + 64 * r < n)
+                    for (int q = lo[r]; q < hi[r]; ++q) {
+                        const uint64_t kq = kk[q];
+                        rk[r] += (kq < mk[r] || (kq == mk[r] && kpid[q] < pd[r])) ? 1 : 0;
+                    }
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < PPL; ++r) {
+            const int np = lo[r] + (rk[r] < hi[r] - lo[r] ? rk[r] : hi[r] - lo[r] - 1);
+            if (lane + 64 * r < n) pos[r] = np;
+        }
+        C *= gl[l];
+    }
+    // hand over to canonical order: slot of the particle at each position
+#pragma unroll
+    for (int r = 0; r < PPL; ++r)
+        if (lane + 64 * r < n) ord[pos[r]] = gi[r];
+    wave_sync();
+    int gp[PPL];
+    double ws[PPL], ps[PPL];
+#pragma unroll
+    for (int r = 0; r < PPL; ++r) {
+        const int p = lane + 64 * r;
+        gp[r] = 0;
+        ws[r] = ps[r] = 0.0;
+        if (p < n) {
+            gp[r] = ord[p];
+            ws[r] = a.in.w[gp[r]];
+            ps[r] = a.in.psi[gp[r]];
+            wacc[2 * p] = ws[r] * ps[r];
+            wacc[2 * p + 1] = ws[r];
+        }
+    }
+    wave_sync();
+    for (int b = lane; b < Cp; b += 64) {
+        const int lo = (int)(((long long)b * n + Cp - 1) / Cp), hi = (int)(((long long)(b + 1) * n + Cp - 1) / Cp);
+        double sw = 0.0, swp = 0.0;
+        for (int q = lo; q < hi; ++q) {
+            swp += wacc[2 * q];
+            sw += wacc[2 * q + 1];
+        }
+        bmean[b] = swp / sw;
+    }
+    wave_sync();
+
+    double fmix = a.dt / a.tm[e];
+    fmix = fmix > 1.0 ? 1.0 : fmix;
+    const ElemGeo* G = a.geo + e;
+    double rs[3][5];
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) rs[v][q] = a.shift[(int64_t)G->node[v] * 5 + q];
+    double acc[3][NPART];
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int q = 0; q < NPART; ++q) acc[v][q] = 0.0;
+#pragma unroll
+    for (int r = 0; r < PPL; ++r) {
+        const int p = lane + 64 * r;
+        if (p >= n) continue;
+        const int64_t g = gp[r];
+        const double x = a.in.x[g], y = a.in.y[g], om = a.in.om[g];
+        const double u0 = a.in.u0[g], u1 = a.in.u1[g], u2 = a.in.u2[g];
+        const uint64_t pid = a.in.pid[g];
+        const int b = (int)(((long long)Cp * p) / n);
+        const double psi = ps[r] - fmix * (ps[r] - bmean[b]);
+        const double w = ws[r];
+        const int64_t o = s0 + p;
+        a.out.x[o] = x;
+        a.out.y[o] = y;
+        a.out.u0[o] = u0;
+        a.out.u1[o] = u1;
+        a.out.u2[o] = u2;
+        a.out.om[o] = om;
+        a.out.psi[o] = psi;
+        a.out.w[o] = w;
+        a.out.pid[o] = pid;
+        a.out.elem[o] = (int32_t)e;
+        double na, nb, nc;
+        area_coords(G, x, y, na, nb, nc);
+        const double lam[3] = {na / G->area, nb / G->area, nc / G->area};
+        const double q5[5] = {u0, u1, u2, om, psi};
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const double wl = w * lam[v];
+            double d[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) d[q] = q5[q] - rs[v][q];
+            acc[v][0] += wl;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) acc[v][1 + q] += wl * d[q];
+            acc[v][6] += wl * d[0] * d[0];
+            acc[v][7] += wl * d[1] * d[1];
+            acc[v][8] += wl * d[2] * d[2];
+            acc[v][9] += wl * d[0] * d[1];
+            acc[v][10] += wl * d[0] * d[2];
+            acc[v][11] += wl * d[1] * d[2];
+            acc[v][12] += wl * d[4] * d[4];
+        }
+    }
+    // fixed-order wavefront reduction through LDS: row q holds the 64 lanes' values
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+#pragma unroll
+        for (int q = 0; q < NPART; ++q) red[q * 65 + lane] = acc[v][q];
+        wave_sync();
+        if (lane < NPART) {
+            double s = 0.0;
+            for (int l = 0; l < 64; ++l) s += red[lane * 65 + l];
+            a.part[e * 3 * NPART + v * NPART + lane] = s;
+        }
+        wave_sync();
     }
 }
 
@@ -638,6 +882,7 @@ __global__ void __launch_bounds__(256) k_node_finalize(NodeArgs a)
     if (i == 0) {
         a.meta[0] = a.start[a.ne];   // used slots after compaction
         a.meta[1] = a.start[a.ne];   // live particles
+        *a.big_count = 0;            // worklist of large elements, empty for the next pass
     }
     if (i >= a.nn) return;
     double S[NPART];
@@ -914,12 +1159,22 @@ void launch_scatter(const int32_t* elem, const int64_t* nslots, int64_t n_ub, in
 }
 hipError_t prepare_element_pass(int lds_max)
 {
-    return hipFuncSetAttribute((const void*)k_element_pass<EP_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    return hipFuncSetAttribute((const void*)k_element_block<EP_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)element_pass_smem(lds_max));
 }
 void launch_element_pass(const ElementArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_element_pass<EP_NT>, dim3((unsigned)a.ne), dim3(EP_NT), element_pass_smem(a.lds_max), s, a);
+    const dim3 g4((unsigned)((a.ne + 3) / 4)), b4(256), g2((unsigned)((a.ne + 1) / 2)), b2(128);
+    switch (a.ppl) {
+    case 1: hipLaunchKernelGGL(k_element_wave<1>, g4, b4, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_element_wave<2>, g4, b4, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_element_wave<3>, g4, b4, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_element_wave<4>, g4, b4, 0, s, a); break;
+    case 5: hipLaunchKernelGGL(k_element_wave<5>, g4, b4, 0, s, a); break;
+    case 6: hipLaunchKernelGGL(k_element_wave<6>, g2, b2, 0, s, a); break;
+    default: hipLaunchKernelGGL(k_element_wave<8>, g2, b2, 0, s, a); break;
+    }
+    hipLaunchKernelGGL(k_element_block<EP_NT>, dim3(EP_BIG_BLOCKS), dim3(EP_NT), element_pass_smem(a.lds_max), s, a);
 }
 void launch_node_finalize(const NodeArgs& a, hipStream_t s)
 {

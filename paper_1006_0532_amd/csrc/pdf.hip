@@ -143,6 +143,9 @@ pdf_status regroup(pdf_ens_s* E, double dt, bool counts_ready, hipStream_t s)
     ea.bins2 = E->d.bins[2];
     ea.minpb = E->d.min_per_bin;
     ea.lds_max = E->lds_max;
+    ea.ppl = E->ppl;
+    ea.big_list = E->big_list;
+    ea.big_count = E->big_count;
     ea.gkey = E->gkey;
     ea.gord = E->gord;
     ea.gu3 = E->gu3;
@@ -160,6 +163,7 @@ pdf_status regroup(pdf_ens_s* E, double dt, bool counts_ready, hipStream_t s)
     na.start = E->start;
     na.ne = g->ne;
     na.meta = E->d_meta;
+    na.big_count = E->big_count;
     {
         Timed t(E, T_NODE, s);
         launch_node_finalize(na, s);
@@ -255,7 +259,8 @@ pdf_status pdf_ens_destroy(pdf_ens E)
     }
     dfree(E->counts); dfree(E->start); dfree(E->idx); dfree(E->scan_tmp); dfree(E->d_meta); dfree(E->part);
     dfree(E->stats); dfree(E->shift); dfree(E->tm); dfree(E->err); dfree(E->cnt); dfree(E->gkey); dfree(E->gord);
-    dfree(E->gu3); dfree(E->ctl_clone); dfree(E->ctl_off); dfree(E->ctl_rep);
+    dfree(E->gu3); dfree(E->ctl_clone); dfree(E->ctl_off); dfree(E->ctl_rep); dfree(E->big_list);
+    dfree(E->big_count);
     delete E;
     return PDF_OK;
 }
@@ -328,32 +333,34 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
     if (st == PDF_OK) st = dalloc(&E->shift, g->nn * 5);
     if (st == PDF_OK) st = dalloc(&E->tm, g->ne);
     if (st == PDF_OK) st = dalloc(&E->err, 1);
-    if (st == PDF_OK) st = dalloc(&E->cnt, NCOUNT);
+    if (st == PDF_OK) st = dalloc(&E->cnt, NCOUNT * CNT_SLOTS);
     if (st == PDF_OK) st = dalloc(&E->gkey, 2 * cap);
     if (st == PDF_OK) st = dalloc(&E->gord, 2 * cap);
     if (st == PDF_OK) st = dalloc(&E->gu3, 4 * cap);
     if (st == PDF_OK) st = dalloc(&E->ctl_clone, g->ne);
     if (st == PDF_OK) st = dalloc(&E->ctl_off, g->ne + 1);
     if (st == PDF_OK) st = dalloc(&E->ctl_rep, 4);
+    if (st == PDF_OK) st = dalloc(&E->big_list, g->ne);
+    if (st == PDF_OK) st = dalloc(&E->big_count, 1);
     if (st != PDF_OK) {
         pdf_ens_destroy(E);
         return st;
     }
-    // particles per element that fit the on-chip path of the element pass
-    int smem = 0;
-    if (hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device) != hipSuccess) smem = 65536;
-    const int fixed = (int)element_pass_smem(0);
-    int per = (int)element_pass_smem(1) - fixed;
-    E->lds_max = std::max(64, std::min(2048, (smem - fixed) / per));
-    if (prepare_element_pass(E->lds_max) != hipSuccess) {
-        (void)hipGetLastError();
-        E->lds_max = std::max(64, std::min(E->lds_max, (65536 - fixed) / per));
+    // element pass: a wavefront per element holds up to 64 * ppl particles (ppl from the
+    // set-up count with 30 % headroom); larger elements go to the workgroup kernel, whose
+    // on-chip path takes up to lds_max particles within 64 KiB of LDS
+    E->ppl = (int)std::min<int64_t>(8, std::max<int64_t>(1, (13 * (int64_t)d.ppe + 639) / 640));
+    if (E->ppl == 7) E->ppl = 8;
+    {
+        const int fixed = (int)element_pass_smem(0);
+        const int per = (int)element_pass_smem(1) - fixed;
+        E->lds_max = std::max(64, (65536 - fixed) / per);
         HIP_TRY(prepare_element_pass(E->lds_max));
     }
-
     launch_fill_i32(E->counts, g->ne, 0, s);
+    launch_fill_i32(E->big_count, 1, 0, s);
     launch_fill_i32(E->idx, cap, 0, s);
-    launch_fill_u64(E->cnt, NCOUNT, 0ull, s);
+    launch_fill_u64(E->cnt, NCOUNT * CNT_SLOTS, 0ull, s);
     launch_fill_i32(reinterpret_cast<int32_t*>(E->err), 1, 0, s);
     launch_fill_i32(E->buf[0].elem, cap, -1, s);
     launch_fill_i32(E->buf[1].elem, cap, -1, s);
@@ -695,9 +702,13 @@ pdf_status pdf_counters(pdf_ens E, int32_t problem, int64_t out[PDF_NCOUNTERS])
     }
     HIP_TRY(hipSetDevice(E->grid->device));
     HIP_TRY(hipStreamSynchronize(E->stream));
-    unsigned long long c[NCOUNT];
-    HIP_TRY(hipMemcpy(c, E->cnt, sizeof(c), hipMemcpyDeviceToHost));
-    for (int q = 0; q < NCOUNT; ++q) out[q] = (int64_t)c[q];
+    std::vector<unsigned long long> c(NCOUNT * CNT_SLOTS);
+    HIP_TRY(hipMemcpy(c.data(), E->cnt, sizeof(unsigned long long) * c.size(), hipMemcpyDeviceToHost));
+    for (int q = 0; q < NCOUNT; ++q) {
+        unsigned long long t = 0;
+        for (int k = 0; k < CNT_SLOTS; ++k) t += c[(size_t)q * CNT_SLOTS + k];
+        out[q] = (int64_t)t;
+    }
     return check_device_error(E);
 }
 

@@ -36,6 +36,7 @@ static_assert(sizeof(ElemGeo) % 16 == 0, "ElemGeo alignment");
 constexpr int NSTAT = PDF_NSTAT;     // statistics per node
 constexpr int NPART = 13;            // partial sums per element vertex
 constexpr int NCOUNT = PDF_NCOUNTERS;
+constexpr int CNT_SLOTS = 256;       // spread copies of every event counter
 
 // device error bits (sticky)
 enum : uint32_t { ERR_LOST = 1u, ERR_NONFINITE = 2u, ERR_CAPACITY = 4u, ERR_BADELEM = 8u };
@@ -99,7 +100,7 @@ struct pdf_ens_s {
     double* shift = nullptr;     // [nn][5] reference values of the single-pass moments
     double* tm = nullptr;        // [ne] micromixing timescale, Eq. (25)
     uint32_t* err = nullptr;     // sticky device error word
-    unsigned long long* cnt = nullptr;  // [NCOUNT]
+    unsigned long long* cnt = nullptr;  // [NCOUNT][CNT_SLOTS]
     // element-pass scratch for elements too large for on-chip memory, [cap] each
     double* gkey = nullptr;      // 2 doubles per particle (key, pid bits)
     int32_t* gord = nullptr;     // 2 ints per particle
@@ -113,6 +114,9 @@ struct pdf_ens_s {
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
     double t_ms[pdfgpu::T_N] = {0};
     int64_t t_n[pdfgpu::T_N] = {0};
-    int lds_max = 0;            // particles per element handled on chip
+    int lds_max = 0;            // particles per element on chip in the workgroup kernel
+    int ppl = 4;                // particles per lane in the wavefront kernel
+    int32_t* big_list = nullptr;
+    int32_t* big_count = nullptr;
     bool ctl_valid = false;     // the current buffer holds the canonical order of a pass
 };

@@ -198,3 +198,31 @@ def test_error_paths(gpu):
     with pytest.raises(gpu.PdfError) as ex:
         gpu.Grid(bad, f, mo)
     assert ex.value.status == -4
+
+
+def test_elements_above_the_wavefront_limit(gpu):
+    """An ensemble seeded with 40 per element holds at most 64 per wavefront; importing
+    600 per element sends every element to the workgroup kernel's on-chip path."""
+    _say("test_elements_above_the_wavefront_limit")
+    mesh = box(4, 4, length=2.0, jitter=0.1)
+    f = W.uniform_fields(mesh, mean_u=(0.3, 0.1, 0.0), mean_omega=4.0)
+    mo = W.model_constants()
+    big = W.init_desc(ppe=600, bins=(4, 4, 2), src_x=1.0, src_r=0.4)
+    og = O.Grid(mesh, f, mo)
+    oe = O.Ensemble(og, big)
+    gg = gpu.Grid(mesh, f, mo)
+    ge = gpu.Ensemble(gg, W.init_desc(ppe=40, bins=(4, 4, 2), src_x=1.0, src_r=0.4),
+                      capacity=700 * mesh.n_elems)
+    st = oe.export()
+    ge.import_state(st, step=0, next_pid=len(st["x"]))
+    frame = og.export()["frame"]
+    compare_stats(ge.stats(), oe.stats())
+    excl = set()
+    for n in range(3):
+        oe.step(1e-3)
+        ge.step(1e-3)
+        rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+    compare_stats(ge.stats(), oe.stats(), _skip_nodes(mesh, excl))
+    ro, rg = oe.control(500, 550), ge.control(500, 550)
+    assert ro == {k: rg[k] for k in ro}
+    compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
