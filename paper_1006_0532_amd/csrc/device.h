@@ -20,20 +20,20 @@ struct Words4 {
 };
 enum : uint32_t { TAG_INIT = 1, TAG_STEP = 2, TAG_WALL_GAMMA = 3, TAG_INIT_GAMMA = 4 };
 
-__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                               uint32_t k0, uint32_t k1)
+__host__ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                        uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-        const uint32_t lo0 = m0 * c0, hi0 = __umulhi(m0, c0);
-        const uint32_t lo1 = m1 * c2, hi1 = __umulhi(m1, c2);
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        // 32 x 32 -> 64-bit products: one v_mad_u64_u32 each on gfx950
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p2 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p2 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p2;
+        c3 = (uint32_t)p0;
         c0 = n0;
-        c1 = lo1;
         c2 = n2;
-        c3 = lo0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -46,14 +46,85 @@ __device__ __forceinline__ Words4 rng_draw(RngKey key, uint64_t pid, uint32_t st
 }
 
 // uniform on the open interval (0, 1): (w + 1/2) * 2^-32, exact in double
-__device__ __forceinline__ double u01(uint32_t w) { return ((double)w + 0.5) * 2.3283064365386962890625e-10; }
+__host__ __device__ __forceinline__ double u01(uint32_t w) { return ((double)w + 0.5) * 2.3283064365386962890625e-10; }
+
+// sin(2 pi u) and cos(2 pi u) for u in [0, 1).  4u is exact, so the quadrant q and the
+// fraction f = 4u - q are exact; folding f > 1/2 onto 1 - f (exact) leaves the angle
+// (pi/2) f <= pi/4, where the Taylor series of sin and cos in f (coefficients
+// (pi/2)^n / n!, rounded from 60-digit arithmetic) converge below 1e-17.
+__host__ __device__ __forceinline__ void sincos_2pi(double u, double& s, double& c)
+{
+    const double t = 4.0 * u;
+    const int q = (int)t;
+    double f = t - (double)q;
+    const bool fold = f > 0.5;
+    if (fold) f = 1.0 - f;
+    const double f2 = f * f;
+    double ps = -0x1.8a404211f9547p-45;
+    ps = fma(ps, f2, 0x1.aaec32af93359p-38);
+    ps = fma(ps, f2, -0x1.6fadb9f155744p-31);
+    ps = fma(ps, f2, 0x1.e8f434d018d63p-25);
+    ps = fma(ps, f2, -0x1.e3074fde8871fp-19);
+    ps = fma(ps, f2, 0x1.50783487ee782p-13);
+    ps = fma(ps, f2, -0x1.32d2cce62bd86p-8);
+    ps = fma(ps, f2, 0x1.466bc6775aae2p-4);
+    ps = fma(ps, f2, -0x1.4abbce625be53p-1);
+    ps = fma(ps, f2, 0x1.921fb54442d18p+0);
+    const double sf = ps * f;
+    double pc = 0x1.ef6e308d6d1c4p-49;
+    pc = fma(pc, f2, -0x1.2a0c591af8314p-41);
+    pc = fma(pc, f2, 0x1.20c62c2f2d7f5p-34);
+    pc = fma(pc, f2, -0x1.b6e24f44b128fp-28);
+    pc = fma(pc, f2, 0x1.f9d38a3763cc3p-22);
+    pc = fma(pc, f2, -0x1.a6d1f2a204a8cp-16);
+    pc = fma(pc, f2, 0x1.e1f506891babbp-11);
+    pc = fma(pc, f2, -0x1.55d3c7e3cbffap-6);
+    pc = fma(pc, f2, 0x1.03c1f081b5ac4p-2);
+    pc = fma(pc, f2, -0x1.3bd3cc9be45dep+0);
+    const double cf = fma(pc, f2, 1.0);
+    const double sp = fold ? cf : sf, cp = fold ? sf : cf;   // sin, cos of (pi/2) * (4u - q)
+    const bool odd = (q & 1) != 0, neg_s = q >= 2, neg_c = q == 1 || q == 2;
+    const double a = odd ? cp : sp, b = odd ? sp : cp;
+    s = neg_s ? -a : a;
+    c = neg_c ? -b : b;
+}
+
+// natural logarithm for u in (0, 1]: u = m 2^e with m in [sqrt(1/2), sqrt(2)); log m =
+// 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.172, summed to s^25; ln 2 split so that e ln2_hi
+// is exact.
+__host__ __device__ __forceinline__ double log_unit(double u)
+{
+    int e;
+    double m = frexp(u, &e);
+    if (m < 0.7071067811865476) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 25.0;
+    p = fma(p, z, 1.0 / 23.0);
+    p = fma(p, z, 1.0 / 21.0);
+    p = fma(p, z, 1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    const double lm = fma(2.0 * s, z * p, 2.0 * s);
+    const double de = (double)e;
+    return fma(de, 0x1.62e42fee00000p-1, fma(de, 0x1.a39ef35793c76p-33, lm));
+}
 
 // Box-Muller: two independent standard normal variates from two uniform words
-__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& z0, double& z1)
+__host__ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& z0, double& z1)
 {
-    const double r = sqrt(-2.0 * log(u01(a)));
+    const double r = sqrt(-2.0 * log_unit(u01(a)));
     double s, c;
-    sincos(6.283185307179586 * u01(b), &s, &c);
+    sincos_2pi(u01(b), s, c);
     z0 = r * c;
     z1 = r * s;
 }

@@ -69,35 +69,48 @@ __global__ void __launch_bounds__(256) k_advance(AdvanceArgs a)
             // (a1) P1 interpolation of the nodal fields (Eq. 37)
             double na, nb, nc;
             area_coords(G, x0, y0, na, nb, nc);
-            const double la = na / G->area, lb = nb / G->area, lc = nc / G->area;
+            const double ia = 1.0 / G->area;
+            const double la = na * ia, lb = nb * ia, lc = nc * ia;
             const double* __restrict__ FA = a.node + (int64_t)G->node[0] * NODE_STRIDE;
             const double* __restrict__ FB = a.node + (int64_t)G->node[1] * NODE_STRIDE;
             const double* __restrict__ FC = a.node + (int64_t)G->node[2] * NODE_STRIDE;
-            double f[21];
-#pragma unroll
-            for (int q = 0; q < 21; ++q) f[q] = la * FA[q] + lb * FB[q] + lc * FC[q];
+            // interpolation in three groups of fields; the empty asm statements keep the
+            // compiler from hoisting all 63 node loads at once (register pressure)
+            auto ip = [&](int q) { return la * FA[q] + lb * FB[q] + lc * FC[q]; };
             const double gu0 = G->gu[0], gu1 = G->gu[1], gu2 = G->gu[2], gu3 = G->gu[3], gu4 = G->gu[4],
                          gu5 = G->gu[5];
 
             // (a2) closure (Eqs. 11, 18, 20)
-            const double R11 = f[NF_RE], R22 = f[NF_RE + 1], R33 = f[NF_RE + 2];
-            const double R12 = f[NF_RE + 3], R13 = f[NF_RE + 4], R23 = f[NF_RE + 5];
-            const double W11 = f[NF_WP], W22 = f[NF_WP + 1], W33 = f[NF_WP + 2];
-            const double W12 = f[NF_WP + 3], W13 = f[NF_WP + 4], W23 = f[NF_WP + 5];
+            const double R11 = ip(NF_RE), R22 = ip(NF_RE + 1), R33 = ip(NF_RE + 2);
+            const double R12 = ip(NF_RE + 3), R13 = ip(NF_RE + 4), R23 = ip(NF_RE + 5);
+            const double Om = ip(NF_OM);
+            asm volatile("" ::: "memory");
             const double k = 0.5 * (R11 + R22 + R33);
-            const double Om = f[NF_OM];
             const double eps = Om * (k + m.nu * m.CT * m.CT * Om);
+            const double prod = -(R11 * gu0 + R12 * gu1 + R12 * gu2 + R22 * gu3 + R13 * gu4 + R23 * gu5);
+            const double W11 = ip(NF_WP), W22 = ip(NF_WP + 1), W33 = ip(NF_WP + 2);
+            const double W12 = ip(NF_WP + 3), W13 = ip(NF_WP + 4), W23 = ip(NF_WP + 5);
+            asm volatile("" ::: "memory");
             const double wpR = W11 * R11 + W22 * R22 + W33 * R33 + 2.0 * (W12 * R12 + W13 * R13 + W23 * R23);
             double c0eps = -2.0 * wpR / (3.0 * k);
             if (c0eps < 0.0) {
                 c0eps = 0.0;
                 clamp = 1;
             }
-            const double prod = -(R11 * gu0 + R12 * gu1 + R12 * gu2 + R22 * gu3 + R13 * gu4 + R23 * gu5);
             const double Sw = m.Cw2 - m.Cw1 * prod / eps;
             const double ik = 1.0 / k;
             const double G11 = (W11 - 0.5 * eps) * ik, G22 = (W22 - 0.5 * eps) * ik, G33 = (W33 - 0.5 * eps) * ik;
             const double G12 = W12 * ik, G13 = W13 * ik, G23 = W23 * ik;
+            double f[21];
+            f[NF_MU] = ip(NF_MU);
+            f[NF_MU + 1] = ip(NF_MU + 1);
+            f[NF_MU + 2] = ip(NF_MU + 2);
+            f[NF_GP] = ip(NF_GP);
+            f[NF_GP + 1] = ip(NF_GP + 1);
+            f[NF_LAP] = ip(NF_LAP);
+            f[NF_LAP + 1] = ip(NF_LAP + 1);
+            f[NF_LAP + 2] = ip(NF_LAP + 2);
+            asm volatile("" ::: "memory");
 
             // random numbers: 6 Gaussians and one uniform (Sec. 3.9)
             const Words4 wA = rng_draw(a.key, pid, a.step, TAG_STEP, 0);
@@ -446,6 +459,16 @@ __device__ __forceinline__ int bin_structure(int n, int b0, int b1, int b2, int 
     return (int)P;
 }
 
+// floor(a / b) for 0 <= a, 0 < b, both below 2^24: single-precision reciprocal estimate,
+// then exact integer correction
+__device__ __forceinline__ int div_small(int a, int b)
+{
+    int q = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
+    while (q * b > a) --q;
+    while ((q + 1) * b <= a) ++q;
+    return q;
+}
+
 // keeps a load index inside [0, n): ranks are unique for unique pids, this only guards
 // memory safety against corrupted input
 __device__ __forceinline__ int clampi(int j, int n) { return j < 0 ? 0 : (j >= n ? n - 1 : j); }
@@ -518,6 +541,7 @@ __device__ __forceinline__ void element_body(const ElementArgs& a, int32_t e, in
     double fmix = a.dt / a.tm[e];
     fmix = fmix > 1.0 ? 1.0 : fmix;
     const ElemGeo* G = a.geo + e;
+    const double inv_area = 1.0 / G->area;
     double rs[3][5];
 #pragma unroll
     for (int v = 0; v < 3; ++v)
@@ -550,7 +574,7 @@ __device__ __forceinline__ void element_body(const ElementArgs& a, int32_t e, in
         a.out.elem[o] = e;
         double na, nb, nc;
         area_coords(G, x, y, na, nb, nc);
-        const double lam[3] = {na / G->area, nb / G->area, nc / G->area};
+        const double lam[3] = {na * inv_area, nb * inv_area, nc * inv_area};
         const double q5[5] = {u0, u1, u2, om, psi};
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
@@ -649,9 +673,10 @@ template <int PPL>
 __global__ void __launch_bounds__(256) k_element_wave(ElementArgs a)
 {
     constexpr int N = 64 * PPL;
-    constexpr int RED = 13 * 65 * 8;                      // transposed reduction, padded rows
+    constexpr int RED = (13 * 65 * 8 + 15) & ~15;         // transposed reduction, padded rows
     constexpr int R1 = (24 * N > RED) ? 24 * N : RED;     // keys / (w psi, w) / reduction
     constexpr int WAVE_BYTES = R1 + 4 * N + 8 * N;
+    static_assert(WAVE_BYTES % 16 == 0 && R1 % 16 == 0, "16-byte aligned LDS slices");
     constexpr int WPB = WaveBlock<PPL>::waves;
     __shared__ __attribute__((aligned(16))) unsigned char sm[WPB * WAVE_BYTES];
     // wave-uniform values go through readfirstlane so that they live in scalar registers
@@ -709,30 +734,45 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs a)
 #pragma unroll
         for (int r = 0; r < PPL; ++r) {
             mk[r] = order_bits(l == 0 ? U0[r] : (l == 1 ? U1[r] : U2[r]));
-            const long long t = C * pos[r] / n;
-            lo[r] = (int)((t * n + C - 1) / C);
-            hi[r] = (int)(((t + 1) * n + C - 1) / C);
+            const int t = div_small((int)C * pos[r], n);
+            lo[r] = div_small(t * n + (int)C - 1, (int)C);
+            hi[r] = div_small((t + 1) * n + (int)C - 1, (int)C);
             if (lane + 64 * r < n) {
                 kk[pos[r]] = mk[r];
                 kpid[pos[r]] = pd[r];
             }
         }
+        // pad the keys to a multiple of 8 with the largest key (never below a real key)
+        const int n8 = (n + 7) & ~7;
+        for (int q = n + lane; q < n8; q += 64) kk[q] = ~0ull;
         wave_sync();
-        // rank inside the group by the velocity key alone (ties are rare)
+        // rank inside the group by the velocity key alone (ties are rare); eight keys per
+        // iteration so that one LDS round trip serves eight comparisons per particle
         int rk[PPL];
 #pragma unroll
         for (int r = 0; r < PPL; ++r) rk[r] = 0;
         if (l == 0) {
-            for (int q = 0; q < n; ++q) {
-                const uint64_t kq = kk[q];
+            for (int q = 0; q < n8; q += 8) {
+                const ulonglong2 k01 = *reinterpret_cast<const ulonglong2*>(kk + q);
+                const ulonglong2 k23 = *reinterpret_cast<const ulonglong2*>(kk + q + 2);
+                const ulonglong2 k45 = *reinterpret_cast<const ulonglong2*>(kk + q + 4);
+                const ulonglong2 k67 = *reinterpret_cast<const ulonglong2*>(kk + q + 6);
 #pragma unroll
-                for (int r = 0; r < PPL; ++r) rk[r] += kq < mk[r] ? 1 : 0;
+                for (int r = 0; r < PPL; ++r)
+                    rk[r] += (k01.x < mk[r]) + (k01.y < mk[r]) + (k23.x < mk[r]) + (k23.y < mk[r]) +
+                             (k45.x < mk[r]) + (k45.y < mk[r]) + (k67.x < mk[r]) + (k67.y < mk[r]);
             }
         } else {
 #pragma unroll
             for (int r = 0; r < PPL; ++r)
-                if (lane + 64 * r < n)
-                    for (int q = lo[r]; q < hi[r]; ++q) rk[r] += kk[q] < mk[r] ? 1 : 0;
+                if (lane + 64 * r < n) {
+                    int q = lo[r];
+                    for (; q + 4 <= hi[r]; q += 4) {
+                        const uint64_t k0 = kk[q], k1 = kk[q + 1], k2 = kk[q + 2], k3 = kk[q + 3];
+                        rk[r] += (k0 < mk[r]) + (k1 < mk[r]) + (k2 < mk[r]) + (k3 < mk[r]);
+                    }
+                    for (; q < hi[r]; ++q) rk[r] += kk[q] < mk[r] ? 1 : 0;
+                }
         }
         // equal keys give equal ranks: detect by claiming the slots, then rank exactly
         // by (key, pid) in that case
@@ -785,7 +825,7 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs a)
     }
     wave_sync();
     for (int b = lane; b < Cp; b += 64) {
-        const int lo = (int)(((long long)b * n + Cp - 1) / Cp), hi = (int)(((long long)(b + 1) * n + Cp - 1) / Cp);
+        const int lo = div_small(b * n + Cp - 1, Cp), hi = div_small((b + 1) * n + Cp - 1, Cp);
         double sw = 0.0, swp = 0.0;
         for (int q = lo; q < hi; ++q) {
             swp += wacc[2 * q];
@@ -798,6 +838,7 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs a)
     double fmix = a.dt / a.tm[e];
     fmix = fmix > 1.0 ? 1.0 : fmix;
     const ElemGeo* G = a.geo + e;
+    const double inv_area = 1.0 / G->area;
     double rs[3][5];
 #pragma unroll
     for (int v = 0; v < 3; ++v)
@@ -816,7 +857,7 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs a)
         const double x = a.in.x[g], y = a.in.y[g], om = a.in.om[g];
         const double u0 = a.in.u0[g], u1 = a.in.u1[g], u2 = a.in.u2[g];
         const uint64_t pid = a.in.pid[g];
-        const int b = (int)(((long long)Cp * p) / n);
+        const int b = div_small(Cp * p, n);
         const double psi = ps[r] - fmix * (ps[r] - bmean[b]);
         const double w = ws[r];
         const int64_t o = s0 + p;
@@ -832,7 +873,7 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs a)
         a.out.elem[o] = (int32_t)e;
         double na, nb, nc;
         area_coords(G, x, y, na, nb, nc);
-        const double lam[3] = {na / G->area, nb / G->area, nc / G->area};
+        const double lam[3] = {na * inv_area, nb * inv_area, nc * inv_area};
         const double q5[5] = {u0, u1, u2, om, psi};
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
