@@ -46,241 +46,233 @@ __device__ __noinline__ bool fallback_search(const ElemGeo* __restrict__ geo, co
     return false;
 }
 
-__global__ void __launch_bounds__(256) k_advance(AdvanceArgs a)
+struct AdvEvents {
+    int ev_a, ev_b, omrefl, clamp, src, steps, refl, fb;
+};
+
+// one particle of the particle loop: returns its new host element (its old one when it
+// could not be tracked)
+__device__ __forceinline__ int32_t advance_one(const AdvanceArgs& a, const int64_t i, const int32_t e, AdvEvents& ev)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t nslots = *a.nslots;
-    int32_t key = -1;
-    int ev_a = 0, ev_b = 0, omrefl = 0, clamp = 0, src = 0, steps = 0, refl = 0, fb = 0;
-    if (i < nslots) {
-        int32_t e = a.s.elem[i];
-        if (e >= a.ne) {
-            atomicOr(a.err, ERR_BADELEM);
-            e = -1;
-        }
-        if (e >= 0) {
-            const ModelC& m = a.m;
-            const ElemGeo* G = a.geo + e;
-            const double x0 = a.s.x[i], y0 = a.s.y[i];
-            const double u0 = a.s.u0[i], u1 = a.s.u1[i], u2 = a.s.u2[i];
-            const double om = a.s.om[i];
-            const uint64_t pid = a.s.pid[i];
+    const ModelC& m = a.m;
+    const ElemGeo* G = a.geo + e;
+    const double x0 = a.s.x[i], y0 = a.s.y[i];
+    const double u0 = a.s.u0[i], u1 = a.s.u1[i], u2 = a.s.u2[i];
+    const double om = a.s.om[i];
+    const uint64_t pid = a.s.pid[i];
 
-            // (a1) P1 interpolation of the nodal fields (Eq. 37)
-            double na, nb, nc;
-            area_coords(G, x0, y0, na, nb, nc);
-            const double ia = 1.0 / G->area;
-            const double la = na * ia, lb = nb * ia, lc = nc * ia;
-            const double* __restrict__ FA = a.node + (int64_t)G->node[0] * NODE_STRIDE;
-            const double* __restrict__ FB = a.node + (int64_t)G->node[1] * NODE_STRIDE;
-            const double* __restrict__ FC = a.node + (int64_t)G->node[2] * NODE_STRIDE;
-            // interpolation in three groups of fields; the empty asm statements keep the
-            // compiler from hoisting all 63 node loads at once (register pressure)
-            auto ip = [&](int q) { return la * FA[q] + lb * FB[q] + lc * FC[q]; };
-            const double gu0 = G->gu[0], gu1 = G->gu[1], gu2 = G->gu[2], gu3 = G->gu[3], gu4 = G->gu[4],
-                         gu5 = G->gu[5];
+    // (a1) P1 interpolation of the nodal fields (Eq. 37)
+    double na, nb, nc;
+    area_coords(G, x0, y0, na, nb, nc);
+    const double ia = 1.0 / G->area;
+    const double la = na * ia, lb = nb * ia, lc = nc * ia;
+    const double* __restrict__ FA = a.node + (int64_t)G->node[0] * NODE_STRIDE;
+    const double* __restrict__ FB = a.node + (int64_t)G->node[1] * NODE_STRIDE;
+    const double* __restrict__ FC = a.node + (int64_t)G->node[2] * NODE_STRIDE;
+    // interpolation in three groups of fields; the empty asm statements keep the
+    // compiler from hoisting all 63 node loads at once (register pressure)
+    auto ip = [&](int q) { return la * FA[q] + lb * FB[q] + lc * FC[q]; };
+    const double gu0 = G->gu[0], gu1 = G->gu[1], gu2 = G->gu[2], gu3 = G->gu[3], gu4 = G->gu[4],
+                 gu5 = G->gu[5];
 
-            // (a2) closure (Eqs. 11, 18, 20)
-            const double R11 = ip(NF_RE), R22 = ip(NF_RE + 1), R33 = ip(NF_RE + 2);
-            const double R12 = ip(NF_RE + 3), R13 = ip(NF_RE + 4), R23 = ip(NF_RE + 5);
-            const double Om = ip(NF_OM);
-            asm volatile("" ::: "memory");
-            const double k = 0.5 * (R11 + R22 + R33);
-            const double eps = Om * (k + m.nu * m.CT * m.CT * Om);
-            const double prod = -(R11 * gu0 + R12 * gu1 + R12 * gu2 + R22 * gu3 + R13 * gu4 + R23 * gu5);
-            const double W11 = ip(NF_WP), W22 = ip(NF_WP + 1), W33 = ip(NF_WP + 2);
-            const double W12 = ip(NF_WP + 3), W13 = ip(NF_WP + 4), W23 = ip(NF_WP + 5);
-            asm volatile("" ::: "memory");
-            const double wpR = W11 * R11 + W22 * R22 + W33 * R33 + 2.0 * (W12 * R12 + W13 * R13 + W23 * R23);
-            double c0eps = -2.0 * wpR / (3.0 * k);
-            if (c0eps < 0.0) {
-                c0eps = 0.0;
-                clamp = 1;
-            }
-            const double Sw = m.Cw2 - m.Cw1 * prod / eps;
-            const double ik = 1.0 / k;
-            const double G11 = (W11 - 0.5 * eps) * ik, G22 = (W22 - 0.5 * eps) * ik, G33 = (W33 - 0.5 * eps) * ik;
-            const double G12 = W12 * ik, G13 = W13 * ik, G23 = W23 * ik;
-            double f[21];
-            f[NF_MU] = ip(NF_MU);
-            f[NF_MU + 1] = ip(NF_MU + 1);
-            f[NF_MU + 2] = ip(NF_MU + 2);
-            f[NF_GP] = ip(NF_GP);
-            f[NF_GP + 1] = ip(NF_GP + 1);
-            f[NF_LAP] = ip(NF_LAP);
-            f[NF_LAP + 1] = ip(NF_LAP + 1);
-            f[NF_LAP + 2] = ip(NF_LAP + 2);
-            asm volatile("" ::: "memory");
-
-            // random numbers: 6 Gaussians and one uniform (Sec. 3.9)
-            const Words4 wA = rng_draw(a.key, pid, a.step, TAG_STEP, 0);
-            const Words4 wB = rng_draw(a.key, pid, a.step, TAG_STEP, 1);
-            double z0, z1, z2, z3, z4, z5;
-            box_muller(wA.w0, wA.w1, z0, z1);
-            box_muller(wA.w2, wA.w3, z2, z3);
-            box_muller(wB.w0, wB.w1, z4, z5);
-            const double sdt = sqrt(a.dt);
-            const double dWx = sdt * z0, dWy = sdt * z1;
-            const double dWp0 = sdt * z2, dWp1 = sdt * z3, dWp2 = sdt * z4, dWo = sdt * z5;
-            const double eta = u01(wB.w2);
-            const double s2nu = sqrt(2.0 * m.nu);
-            const double sc0 = sqrt(c0eps);
-
-            // velocity, Eq. (27)
-            const double d0 = u0 - f[NF_MU], d1 = u1 - f[NF_MU + 1], d2 = u2 - f[NF_MU + 2];
-            const double irho = 1.0 / m.rho;
-            const double dr0 = -f[NF_GP] * irho + 2.0 * m.nu * f[NF_LAP] + G11 * d0 + G12 * d1 + G13 * d2;
-            const double dr1 = -f[NF_GP + 1] * irho + 2.0 * m.nu * f[NF_LAP + 1] + G12 * d0 + G22 * d1 + G23 * d2;
-            const double dr2 = 2.0 * m.nu * f[NF_LAP + 2] + G13 * d0 + G23 * d1 + G33 * d2;
-            double v0 = u0 + dr0 * a.dt + s2nu * (gu0 * dWx + gu1 * dWy) + sc0 * dWp0;
-            double v1 = u1 + dr1 * a.dt + s2nu * (gu2 * dWx + gu3 * dWy) + sc0 * dWp1;
-            double v2 = u2 + dr2 * a.dt + s2nu * (gu4 * dWx + gu5 * dWy) + sc0 * dWp2;
-            // frequency, Eq. (19): |omega| in the diffusion, reflected at zero
-            double omn = om - m.C3 * Om * (om - Om) * a.dt - Sw * Om * om * a.dt +
-                         sqrt(2.0 * m.C3 * m.C4 * Om * Om * fabs(om)) * dWo;
-            if (omn < 0.0) {
-                omn = -omn;
-                omrefl = 1;
-            }
-            // position, Eq. (7), with the start-of-step velocity
-            double x = x0 + u0 * a.dt + s2nu * dWx;
-            double y = y0 + u1 * a.dt + s2nu * dWy;
-
-            // (a3) next-best-element walk (Sec. 3.6) with particle wall conditions (Sec. 3.8)
-            int32_t c = e;
-            double shift = 0.0;
-            bool found = false;
-            int wall_a = 0;
-            for (int it = 0; it < 64; ++it) {
-                const ElemGeo* C = a.geo + c;
-                double ma, mb, mc;
-                area_coords(C, x, y, ma, mb, mc);
-                if (ma >= 0.0 && mb >= 0.0 && mc >= 0.0) {
-                    found = true;
-                    break;
-                }
-                int kk = 0;
-                double mn = ma;
-                if (mb < mn) {
-                    kk = 1;
-                    mn = mb;
-                }
-                if (mc < mn) kk = 2;
-                const uint8_t kd = C->kind[kk];
-                if (kd == KIND_INTERIOR) {
-                    c = C->nbr[kk];
-                    ++steps;
-                    continue;
-                }
-                if (kd == KIND_PERIODIC) {
-                    x += C->shift[kk];
-                    shift += C->shift[kk];
-                    c = C->nbr[kk];
-                    ++steps;
-                    continue;
-                }
-                int32_t fe;
-                double off;
-                if (fallback_search(a.geo, a.n2e_ptr, a.n2e, c, x, y, fe, off)) {
-                    c = fe;
-                    x += off;
-                    shift += off;
-                    ++fb;
-                    continue;
-                }
-                if (refl == 4) break;
-                // mirror across the line of edge kk (vertex kk+1 -> kk+2, interior on the left)
-                const int pa = (kk + 1) % 3, pb = (kk + 2) % 3;
-                const double ax = C->x[pa], ay = C->y[pa];
-                const double ex = C->x[pb] - ax, ey = C->y[pb] - ay;
-                const double len = sqrt(ex * ex + ey * ey);
-                const double nx = -ey / len, ny = ex / len;
-                const double dd = (x - ax) * nx + (y - ay) * ny;
-                x = x - 2.0 * dd * nx;
-                y = y - 2.0 * dd * ny;
-                if (kd == KIND_WALL) {
-                    wall_a = 1;
-                } else {
-                    const double un = v0 * nx + v1 * ny;
-                    v0 = v0 - 2.0 * un * nx;
-                    v1 = v1 - 2.0 * un * ny;
-                }
-                ++refl;
-            }
-            if (!found) {
-                atomicOr(a.err, ERR_LOST);
-                key = e;   // the particle keeps its start-of-step state
-            } else {
-                // no-slip events: (a) crossed the wall; (b) Eq. (53) in wall elements
-                bool hit = wall_a != 0;
-                const ElemGeo* C = a.geo + c;
-                if (!hit && C->wall && m.nu * a.dt > 0.0) {
-                    double dn = (x0 + shift - C->wl[0]) * C->wl[2] + (y0 - C->wl[1]) * C->wl[3];
-                    double dn1 = (x - C->wl[0]) * C->wl[2] + (y - C->wl[1]) * C->wl[3];
-                    dn = dn < 0.0 ? 0.0 : dn;
-                    dn1 = dn1 < 0.0 ? 0.0 : dn1;
-                    const double fw = exp(-dn * dn1 / (m.nu * a.dt));
-                    if (eta < fw) {
-                        hit = true;
-                        ev_b = 1;
-                    }
-                }
-                if (hit) {
-                    ev_a = wall_a;
-                    double pa_, pb_, pc_;
-                    area_coords(C, x, y, pa_, pb_, pc_);
-                    const double* __restrict__ HA = a.node + (int64_t)C->node[0] * NODE_STRIDE;
-                    const double* __restrict__ HB = a.node + (int64_t)C->node[1] * NODE_STRIDE;
-                    const double* __restrict__ HC = a.node + (int64_t)C->node[2] * NODE_STRIDE;
-                    const double omw = (pa_ / C->area) * HA[NF_OM] + (pb_ / C->area) * HB[NF_OM] +
-                                       (pc_ / C->area) * HC[NF_OM];
-                    v0 = v1 = v2 = 0.0;
-                    omn = gamma_draw(1.0 / m.C4, omw, a.key, pid, a.step, TAG_WALL_GAMMA);
-                }
-                a.s.x[i] = x;
-                a.s.y[i] = y;
-                a.s.u0[i] = v0;
-                a.s.u1[i] = v1;
-                a.s.u2[i] = v2;
-                a.s.om[i] = omn;
-                a.s.elem[i] = c;
-                if (a.src_cont) {
-                    double dx = x - a.src_x, dy = y - a.src_y;
-                    if (a.period > 0.0) {
-                        if (dx > 0.5 * a.period) dx -= a.period;
-                        else if (dx < -0.5 * a.period) dx += a.period;
-                    }
-                    if (dx * dx + dy * dy < a.src_r2) {
-                        a.s.psi[i] = 1.0;
-                        src = 1;
-                    }
-                }
-                if (!(isfinite(x) && isfinite(y) && isfinite(v0) && isfinite(v1) && isfinite(v2) && isfinite(omn)))
-                    atomicOr(a.err, ERR_NONFINITE);
-                key = c;
-            }
-        }
+    // (a2) closure (Eqs. 11, 18, 20)
+    const double R11 = ip(NF_RE), R22 = ip(NF_RE + 1), R33 = ip(NF_RE + 2);
+    const double R12 = ip(NF_RE + 3), R13 = ip(NF_RE + 4), R23 = ip(NF_RE + 5);
+    const double Om = ip(NF_OM);
+    asm volatile("" ::: "memory");
+    const double k = 0.5 * (R11 + R22 + R33);
+    const double eps = Om * (k + m.nu * m.CT * m.CT * Om);
+    const double prod = -(R11 * gu0 + R12 * gu1 + R12 * gu2 + R22 * gu3 + R13 * gu4 + R23 * gu5);
+    const double W11 = ip(NF_WP), W22 = ip(NF_WP + 1), W33 = ip(NF_WP + 2);
+    const double W12 = ip(NF_WP + 3), W13 = ip(NF_WP + 4), W23 = ip(NF_WP + 5);
+    asm volatile("" ::: "memory");
+    const double wpR = W11 * R11 + W22 * R22 + W33 * R33 + 2.0 * (W12 * R12 + W13 * R13 + W23 * R23);
+    double c0eps = -2.0 * wpR / (3.0 * k);
+    if (c0eps < 0.0) {
+        c0eps = 0.0;
+        ev.clamp = 1;
     }
-    // (a4, first half) particles per new host element: runs of equal keys share one atomic
-    int leader, len, rank;
-    wave_runs(key, leader, len, rank);
-    if (rank == 0 && key >= 0) atomicAdd(a.counts + key, len);
+    const double Sw = m.Cw2 - m.Cw1 * prod / eps;
+    const double ik = 1.0 / k;
+    const double G11 = (W11 - 0.5 * eps) * ik, G22 = (W22 - 0.5 * eps) * ik, G33 = (W33 - 0.5 * eps) * ik;
+    const double G12 = W12 * ik, G13 = W13 * ik, G23 = W23 * ik;
+    double f[21];
+    f[NF_MU] = ip(NF_MU);
+    f[NF_MU + 1] = ip(NF_MU + 1);
+    f[NF_MU + 2] = ip(NF_MU + 2);
+    f[NF_GP] = ip(NF_GP);
+    f[NF_GP + 1] = ip(NF_GP + 1);
+    f[NF_LAP] = ip(NF_LAP);
+    f[NF_LAP + 1] = ip(NF_LAP + 1);
+    f[NF_LAP + 2] = ip(NF_LAP + 2);
+    asm volatile("" ::: "memory");
 
-    // event counters: wavefront sums, then one workgroup sum per counter added to one of
-    // CNT_SLOTS spread copies (no single hot address)
+    // random numbers: 6 Gaussians and one uniform (Sec. 3.9)
+    const Words4 wA = rng_draw(a.key, pid, a.step, TAG_STEP, 0);
+    const Words4 wB = rng_draw(a.key, pid, a.step, TAG_STEP, 1);
+    double z0, z1, z2, z3, z4, z5;
+    box_muller(wA.w0, wA.w1, z0, z1);
+    box_muller(wA.w2, wA.w3, z2, z3);
+    box_muller(wB.w0, wB.w1, z4, z5);
+    const double sdt = sqrt(a.dt);
+    const double dWx = sdt * z0, dWy = sdt * z1;
+    const double dWp0 = sdt * z2, dWp1 = sdt * z3, dWp2 = sdt * z4, dWo = sdt * z5;
+    const double eta = u01(wB.w2);
+    const double s2nu = sqrt(2.0 * m.nu);
+    const double sc0 = sqrt(c0eps);
+
+    // velocity, Eq. (27)
+    const double d0 = u0 - f[NF_MU], d1 = u1 - f[NF_MU + 1], d2 = u2 - f[NF_MU + 2];
+    const double irho = 1.0 / m.rho;
+    const double dr0 = -f[NF_GP] * irho + 2.0 * m.nu * f[NF_LAP] + G11 * d0 + G12 * d1 + G13 * d2;
+    const double dr1 = -f[NF_GP + 1] * irho + 2.0 * m.nu * f[NF_LAP + 1] + G12 * d0 + G22 * d1 + G23 * d2;
+    const double dr2 = 2.0 * m.nu * f[NF_LAP + 2] + G13 * d0 + G23 * d1 + G33 * d2;
+    double v0 = u0 + dr0 * a.dt + s2nu * (gu0 * dWx + gu1 * dWy) + sc0 * dWp0;
+    double v1 = u1 + dr1 * a.dt + s2nu * (gu2 * dWx + gu3 * dWy) + sc0 * dWp1;
+    double v2 = u2 + dr2 * a.dt + s2nu * (gu4 * dWx + gu5 * dWy) + sc0 * dWp2;
+    // frequency, Eq. (19): |omega| in the diffusion, reflected at zero
+    double omn = om - m.C3 * Om * (om - Om) * a.dt - Sw * Om * om * a.dt +
+                 sqrt(2.0 * m.C3 * m.C4 * Om * Om * fabs(om)) * dWo;
+    if (omn < 0.0) {
+        omn = -omn;
+        ev.omrefl = 1;
+    }
+    // position, Eq. (7), with the start-of-step velocity
+    double x = x0 + u0 * a.dt + s2nu * dWx;
+    double y = y0 + u1 * a.dt + s2nu * dWy;
+
+    // (a3) next-best-element walk (Sec. 3.6) with particle wall conditions (Sec. 3.8)
+    int32_t c = e;
+    double shift = 0.0;
+    bool found = false;
+    int wall_a = 0;
+    for (int it = 0; it < 64; ++it) {
+        const ElemGeo* C = a.geo + c;
+        double ma, mb, mc;
+        area_coords(C, x, y, ma, mb, mc);
+        if (ma >= 0.0 && mb >= 0.0 && mc >= 0.0) {
+            found = true;
+            break;
+        }
+        int kk = 0;
+        double mn = ma;
+        if (mb < mn) {
+            kk = 1;
+            mn = mb;
+        }
+        if (mc < mn) kk = 2;
+        const uint8_t kd = C->kind[kk];
+        if (kd == KIND_INTERIOR) {
+            c = C->nbr[kk];
+            ++ev.steps;
+            continue;
+        }
+        if (kd == KIND_PERIODIC) {
+            x += C->shift[kk];
+            shift += C->shift[kk];
+            c = C->nbr[kk];
+            ++ev.steps;
+            continue;
+        }
+        int32_t fe;
+        double off;
+        if (fallback_search(a.geo, a.n2e_ptr, a.n2e, c, x, y, fe, off)) {
+            c = fe;
+            x += off;
+            shift += off;
+            ++ev.fb;
+            continue;
+        }
+        if (ev.refl == 4) break;
+        // mirror across the line of edge kk (vertex kk+1 -> kk+2, interior on the left)
+        const int pa = (kk + 1) % 3, pb = (kk + 2) % 3;
+        const double ax = C->x[pa], ay = C->y[pa];
+        const double ex = C->x[pb] - ax, ey = C->y[pb] - ay;
+        const double len = sqrt(ex * ex + ey * ey);
+        const double nx = -ey / len, ny = ex / len;
+        const double dd = (x - ax) * nx + (y - ay) * ny;
+        x = x - 2.0 * dd * nx;
+        y = y - 2.0 * dd * ny;
+        if (kd == KIND_WALL) {
+            wall_a = 1;
+        } else {
+            const double un = v0 * nx + v1 * ny;
+            v0 = v0 - 2.0 * un * nx;
+            v1 = v1 - 2.0 * un * ny;
+        }
+        ++ev.refl;
+    }
+    if (!found) {
+        atomicOr(a.err, ERR_LOST);
+        return e;   // the particle keeps its start-of-step state
+    } else {
+        // no-slip events: (a) crossed the wall; (b) Eq. (53) in wall elements
+        bool hit = wall_a != 0;
+        const ElemGeo* C = a.geo + c;
+        if (!hit && C->wall && m.nu * a.dt > 0.0) {
+            double dn = (x0 + shift - C->wl[0]) * C->wl[2] + (y0 - C->wl[1]) * C->wl[3];
+            double dn1 = (x - C->wl[0]) * C->wl[2] + (y - C->wl[1]) * C->wl[3];
+            dn = dn < 0.0 ? 0.0 : dn;
+            dn1 = dn1 < 0.0 ? 0.0 : dn1;
+            const double fw = exp(-dn * dn1 / (m.nu * a.dt));
+            if (eta < fw) {
+                hit = true;
+                ev.ev_b = 1;
+            }
+        }
+        if (hit) {
+            ev.ev_a = wall_a;
+            double pa_, pb_, pc_;
+            area_coords(C, x, y, pa_, pb_, pc_);
+            const double* __restrict__ HA = a.node + (int64_t)C->node[0] * NODE_STRIDE;
+            const double* __restrict__ HB = a.node + (int64_t)C->node[1] * NODE_STRIDE;
+            const double* __restrict__ HC = a.node + (int64_t)C->node[2] * NODE_STRIDE;
+            const double omw = (pa_ / C->area) * HA[NF_OM] + (pb_ / C->area) * HB[NF_OM] +
+                               (pc_ / C->area) * HC[NF_OM];
+            v0 = v1 = v2 = 0.0;
+            omn = gamma_draw(1.0 / m.C4, omw, a.key, pid, a.step, TAG_WALL_GAMMA);
+        }
+        a.s.x[i] = x;
+        a.s.y[i] = y;
+        a.s.u0[i] = v0;
+        a.s.u1[i] = v1;
+        a.s.u2[i] = v2;
+        a.s.om[i] = omn;
+        a.s.elem[i] = c;
+        if (a.src_cont) {
+            double dx = x - a.src_x, dy = y - a.src_y;
+            if (a.period > 0.0) {
+                if (dx > 0.5 * a.period) dx -= a.period;
+                else if (dx < -0.5 * a.period) dx += a.period;
+            }
+            if (dx * dx + dy * dy < a.src_r2) {
+                a.s.psi[i] = 1.0;
+                ev.src = 1;
+            }
+        }
+        if (!(isfinite(x) && isfinite(y) && isfinite(v0) && isfinite(v1) && isfinite(v2) && isfinite(omn)))
+            atomicOr(a.err, ERR_NONFINITE);
+        return c;
+    }
+}
+
+// event counters: wavefront sums, then one workgroup sum per counter added to one of
+// CNT_SLOTS spread copies (no single hot address)
+__device__ __forceinline__ void flush_events(const AdvanceArgs& a, const AdvEvents& ev)
+{
     const int lane = lane_id(), wid = threadIdx.x >> 6;
     __shared__ int wsum[4][NCOUNT];
     int v[NCOUNT];
-    v[0] = __popcll(__ballot(ev_a != 0));
-    v[1] = __popcll(__ballot(ev_b != 0));
-    v[4] = __popcll(__ballot(omrefl != 0));
-    v[5] = __popcll(__ballot(clamp != 0));
-    v[7] = __popcll(__ballot(src != 0));
+    v[0] = __popcll(__ballot(ev.ev_a != 0));
+    v[1] = __popcll(__ballot(ev.ev_b != 0));
+    v[4] = __popcll(__ballot(ev.omrefl != 0));
+    v[5] = __popcll(__ballot(ev.clamp != 0));
+    v[7] = __popcll(__ballot(ev.src != 0));
     v[2] = v[3] = v[6] = 0;
-    if (__ballot(steps != 0 || refl != 0 || fb != 0)) {
-        v[6] = wave_sum_int(steps);
-        v[2] = wave_sum_int(refl);
-        v[3] = wave_sum_int(fb);
+    if (__ballot(ev.steps != 0 || ev.refl != 0 || ev.fb != 0)) {
+        v[6] = wave_sum_int(ev.steps);
+        v[2] = wave_sum_int(ev.refl);
+        v[3] = wave_sum_int(ev.fb);
     }
     if (lane == 0)
         for (int q = 0; q < NCOUNT; ++q) wsum[wid][q] = v[q];
@@ -290,6 +282,33 @@ __global__ void __launch_bounds__(256) k_advance(AdvanceArgs a)
         const int tot = wsum[0][q] + wsum[1][q] + wsum[2][q] + wsum[3][q];
         if (tot) atomicAdd(a.cnt + q * CNT_SLOTS + (blockIdx.x & (CNT_SLOTS - 1)), (unsigned long long)tot);
     }
+}
+
+// particles per new host element: runs of equal keys among the lanes share one atomic
+__device__ __forceinline__ void count_new_hosts(const AdvanceArgs& a, int32_t key)
+{
+    int leader, len, rank;
+    wave_runs(key, leader, len, rank);
+    if (rank == 0 && key >= 0) atomicAdd(a.counts + key, len);
+}
+
+// Particle loop: one thread per used slot (merged particles are dead slots, elem < 0)
+__global__ void __launch_bounds__(256) k_advance(AdvanceArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nslots = *a.nslots;
+    int32_t key = -1;
+    AdvEvents ev = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < nslots) {
+        int32_t e = a.s.elem[i];
+        if (e >= a.ne) {
+            atomicOr(a.err, ERR_BADELEM);
+            e = -1;
+        }
+        if (e >= 0) key = advance_one(a, i, e, ev);
+    }
+    count_new_hosts(a, key);
+    flush_events(a, ev);
 }
 
 // =====================================================================================

@@ -226,3 +226,21 @@ def test_elements_above_the_wavefront_limit(gpu):
     ro, rg = oe.control(500, 550), ge.control(500, 550)
     assert ro == {k: rg[k] for k in ro}
     compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+
+
+def test_one_particle_bins_and_many_bins(gpu):
+    """min_per_bin = 1 (workgroup kernel) and a 5x5x5 request (many groups per level)."""
+    _say("test_one_particle_bins_and_many_bins")
+    mesh = box(6, 6, length=2.0)
+    f = W.uniform_fields(mesh, mean_u=(0.3, 0.1, 0.0), mean_omega=4.0)
+    mo = W.model_constants()
+    for bins, m in [((5, 5, 5), 1), ((5, 5, 5), 2), ((8, 4, 4), 2)]:
+        ini = W.init_desc(ppe=150, bins=bins, min_per_bin=m, src_x=1.0, src_r=0.4)
+        og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+        frame = og.export()["frame"]
+        excl = set()
+        for n in range(3):
+            oe.step(2e-3)
+            ge.step(2e-3)
+            rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+        compare_stats(ge.stats(), oe.stats(), _skip_nodes(mesh, excl))
