@@ -10,6 +10,7 @@ sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -30,6 +31,27 @@ BYTES_PER_PARTICLE = {
     # read elem, write idx
     "scatter": 4 + 4,
 }
+
+
+KERNEL_NAMES = {"advance": "k_advance", "element_pass": "k_element_wave", "scatter": "k_scatter"}
+COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_channel_large.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1006_0532_amd", "csrc", "kernels.hip")
+
+
+def counter_traffic(kernel, default_workload):
+    """HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE) from the committed rocprofv3
+    counter summary of this workload, or None if the kernels changed since it was taken."""
+    if not default_workload or not os.path.exists(COUNTERS):
+        return None
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    text = open(COUNTERS).read().splitlines()
+    if f"kernels.hip sha256 prefix: {sha}" not in text:
+        return None
+    for line in text:
+        f = line.split()
+        if len(f) == 3 and f[0] == "traffic_bytes_per_launch" and f[1] == KERNEL_NAMES.get(kernel):
+            return float(f[2])
+    return None
 
 
 def parse():
@@ -137,8 +159,12 @@ def main():
     if dom in BYTES_PER_PARTICLE:
         avg_ms = kern[dom][0] / kern[dom][1]
         achieved = BYTES_PER_PARTICLE[dom] * mean_live / (avg_ms * 1e-3) / 1e9
+        default = (args.nx, args.ny, args.ppe) == (400, 500, 200)
+        traffic = counter_traffic(dom, default)
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic / 1e9, 3),
+                "traffic_unit": "GB per launch",
                 "avg_ms": round(avg_ms, 4), "bytes_per_particle": BYTES_PER_PARTICLE[dom]}
     per_kernel = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches": v[1]} for k, v in kern.items()}
     for k, bpp in BYTES_PER_PARTICLE.items():
