@@ -196,6 +196,180 @@ def uniform_fields(mesh: Mesh, *, grad_p=(0.0, 0.0), wp=(-0.1, -0.1, -0.1, 0, 0,
 
 
 # ---------------------------------------------------------------------------------
+# street canyon: square cavity under a periodic channel
+# ---------------------------------------------------------------------------------
+
+def _cluster_both(a: float, b: float, n: int, beta: float) -> np.ndarray:
+    """n+1 points from a to b, tanh-clustered towards both ends."""
+    s = np.arange(n + 1, dtype=np.float64) / n
+    xi = 0.5 * (1.0 + np.tanh(beta * (2.0 * s - 1.0)) / math.tanh(beta))
+    xi[0], xi[-1] = 0.0, 1.0
+    return a + (b - a) * xi
+
+
+def _cluster_low(a: float, b: float, n: int, beta: float) -> np.ndarray:
+    """n+1 points from a to b, tanh-clustered towards a."""
+    s = np.arange(n + 1, dtype=np.float64) / n
+    xi = 1.0 + np.tanh(beta * (s - 1.0)) / math.tanh(beta)
+    xi[0], xi[-1] = 0.0, 1.0
+    return a + (b - a) * xi
+
+
+def _incircle(ax, ay, bx, by, cx, cy, dx, dy):
+    """> 0 when d lies inside the circumcircle of the counter-clockwise triangle abc."""
+    adx, ady, bdx, bdy, cdx, cdy = ax - dx, ay - dy, bx - dx, by - dy, cx - dx, cy - dy
+    return ((adx * adx + ady * ady) * (bdx * cdy - cdx * bdy)
+            - (bdx * bdx + bdy * bdy) * (adx * cdy - cdx * ady)
+            + (cdx * cdx + cdy * cdy) * (adx * bdy - bdx * ady))
+
+
+def cavity_mesh(nxh: int, ny_channel: int, ny_cavity: int, *, H: float = 1.0, jitter: float = 0.1,
+                beta: float = 1.6, seed: int = MASTER_SEED) -> Mesh:
+    """Street canyon: a square H x H cavity (x in [H, 2H], y in [0, H]) under a channel
+    of height H (y in [H, 2H]) that is periodic in x over 3H (Sec. 4.2 geometry).
+
+    Node columns: nxh cells across the cavity and 2*nxh across the rest of the period,
+    both tanh-clustered towards the cavity's side walls; rows: ny_cavity cells in the
+    cavity clustered towards its floor and its top corners, ny_channel cells in the
+    channel clustered towards the street level y = H.  Interior nodes are jittered by
+    U(-jitter, jitter) of the smaller adjacent spacing (the seam column x = 0, the
+    columns x = H, 2H and the rows y = 0, H, 2H stay fixed).  Every quad is split along
+    its Delaunay diagonal (one Lawson test per quad; cocircular quads take a seeded
+    random diagonal).  Boundaries: no-slip street level, cavity walls and floor;
+    free-slip top y = 2H.  About 2 (3 nxh ny_channel + nxh ny_cavity) triangles.
+    """
+    rng = np.random.default_rng(seed)
+    L = 3.0 * H
+    cav = _cluster_both(H, 2 * H, nxh, beta)                # [H, 2H]
+    out = _cluster_both(2 * H, 4 * H, 2 * nxh, beta)        # [2H, 4H] = [2H, 3H) + [0, H) wrapped
+    xs = np.concatenate([out[nxh:2 * nxh] - L, cav[:nxh], out[:nxh]])     # [0, 3H), 3 nxh columns
+    ncol, iH, i2H = 3 * nxh, nxh, 2 * nxh
+    yc = _cluster_low(H, 2 * H, ny_channel, beta)           # channel rows, y = H first
+    yv = _cluster_both(0.0, H, ny_cavity, beta)[::-1]       # cavity rows, y = H first
+
+    # channel block: rows 0..ny_channel, all columns; cavity block: rows 1..ny_cavity of
+    # columns iH..i2H
+    X = np.tile(xs, (ny_channel + 1, 1))
+    Y = np.tile(yc[:, None], (1, ncol))
+    ncv = nxh + 1
+    XV = np.tile(xs[iH:i2H + 1], (ny_cavity, 1))
+    YV = np.tile(yv[1:, None], (1, ncv))
+
+    dxs = np.diff(np.append(xs, L))                        # spacing to the right of each column
+    left = np.roll(dxs, 1)
+    hx = np.minimum(dxs, left)
+    for j in range(1, ny_channel):
+        hy = min(yc[j] - yc[j - 1], yc[j + 1] - yc[j])
+        cols = np.ones(ncol, bool)
+        cols[[0, iH, i2H]] = False
+        X[j, cols] += rng.uniform(-jitter, jitter, cols.sum()) * hx[cols]
+        Y[j, cols] += rng.uniform(-jitter, jitter, cols.sum()) * hy
+    for j in range(ny_cavity - 1):          # cavity rows 1..ny_cavity-1 (row ny_cavity is the floor)
+        r = j + 1
+        hy = min(yv[r - 1] - yv[r], yv[r] - yv[r + 1])
+        inner = slice(1, ncv - 1)
+        XV[j, inner] += rng.uniform(-jitter, jitter, ncv - 2) * hx[iH + 1:i2H]
+        YV[j, inner] += rng.uniform(-jitter, jitter, ncv - 2) * hy
+    xy = np.concatenate([np.stack([X.ravel(), Y.ravel()], 1), np.stack([XV.ravel(), YV.ravel()], 1)])
+    base = (ny_channel + 1) * ncol
+
+    quads = []
+    # channel quads: lower row j, upper row j+1 (y grows with j)
+    J, I = np.meshgrid(np.arange(ny_channel), np.arange(ncol), indexing="ij")
+    IP = (I + 1) % ncol
+    quads.append(np.stack([J * ncol + I, J * ncol + IP, (J + 1) * ncol + IP, (J + 1) * ncol + I], -1).reshape(-1, 4))
+
+    # cavity quads: upper row r (r = 0 is the channel's street row), lower row r+1
+    def vid(r, c):          # c = 0..nxh relative to column iH
+        return np.where(r == 0, (iH + c) % ncol, base + (r - 1) * ncv + c)
+    R, Cc = np.meshgrid(np.arange(ny_cavity), np.arange(nxh), indexing="ij")
+    quads.append(np.stack([vid(R + 1, Cc), vid(R + 1, Cc + 1), vid(R, Cc + 1), vid(R, Cc)], -1).reshape(-1, 4))
+    q = np.concatenate(quads).astype(np.int64)
+
+    # unwrap the seam for the geometric tests
+    P = xy[q]                                   # [nq, 4, 2]
+    span = P[:, :, 0].max(1) - P[:, :, 0].min(1)
+    wrap = span > 0.5 * L
+    P[wrap, :, 0] = np.where(P[wrap, :, 0] < 0.5 * L, P[wrap, :, 0] + L, P[wrap, :, 0])
+    inc = _incircle(P[:, 0, 0], P[:, 0, 1], P[:, 1, 0], P[:, 1, 1], P[:, 2, 0], P[:, 2, 1], P[:, 3, 0], P[:, 3, 1])
+    scale = np.abs(P[:, 2, 0] - P[:, 0, 0]) + np.abs(P[:, 2, 1] - P[:, 0, 1])
+    tie = np.abs(inc) <= 1e-12 * scale ** 4
+    # diagonal 0-2 is Delaunay when vertex 3 is outside the circumcircle of (0, 1, 2)
+    use02 = np.where(tie, rng.integers(0, 2, len(q)) == 0, inc <= 0)
+    t0 = np.where(use02[:, None], q[:, [0, 1, 2]], q[:, [0, 1, 3]])
+    t1 = np.where(use02[:, None], q[:, [0, 2, 3]], q[:, [1, 2, 3]])
+    tri = np.stack([t0, t1], 1).reshape(-1, 3).astype(np.int32)
+
+    # boundary edges: edges of one element; the top row is free-slip, everything else no-slip
+    e = np.concatenate([np.sort(tri[:, [(k + 1) % 3, (k + 2) % 3]], 1) for k in range(3)])
+    key = e[:, 0].astype(np.int64) * xy.shape[0] + e[:, 1]
+    _, inv, cnt = np.unique(key, return_inverse=True, return_counts=True)
+    single = (cnt[inv] == 1).reshape(3, -1).T
+    top = (np.arange(xy.shape[0]) >= ny_channel * ncol) & (np.arange(xy.shape[0]) < base)
+    kind = np.zeros(tri.shape, np.uint8)
+    for k in range(3):
+        a, b = tri[:, (k + 1) % 3], tri[:, (k + 2) % 3]
+        kind[single[:, k], k] = np.where(top[a] & top[b], EDGE_SLIP, EDGE_WALL)[single[:, k]]
+    return Mesh(xy=xy, tri=tri, edge_kind=kind, period_x=L,
+                meta=dict(kind="cavity", nxh=nxh, ny_channel=ny_channel, ny_cavity=ny_cavity, H=H,
+                          jitter=jitter, beta=beta, seed=seed))
+
+
+def _wall_distance_cavity(x: np.ndarray, y: np.ndarray, H: float) -> np.ndarray:
+    """Distance to the nearest no-slip wall of the street canyon (periodic in x)."""
+    L = 3.0 * H
+    xm = np.mod(x, L)
+
+    def seg(ax, ay, bx, by):
+        best = np.full(x.shape, np.inf)
+        for sh in (-L, 0.0, L):
+            px, py = xm + sh, y
+            vx, vy = bx - ax, by - ay
+            t = np.clip(((px - ax) * vx + (py - ay) * vy) / (vx * vx + vy * vy), 0.0, 1.0)
+            best = np.minimum(best, np.hypot(px - ax - t * vx, py - ay - t * vy))
+        return best
+    d = seg(0.0, H, H, H)
+    d = np.minimum(d, seg(2 * H, H, 3 * H, H))
+    d = np.minimum(d, seg(H, 0.0, H, H))
+    d = np.minimum(d, seg(2 * H, 0.0, 2 * H, H))
+    return np.minimum(d, seg(H, 0.0, 2 * H, 0.0))
+
+
+def cavity_fields(mesh: Mesh, *, recirc: float = 0.1, u_tau: float = 0.1, z0: float = 0.01,
+                  wp_diag: float = -0.1, r_diag: float = 0.05 ** 2) -> Fields:
+    """Analytic street-canyon fields at the nodes.
+
+    In the cavity (y < H) the mean velocity is the recirculation of the stream
+    function recirc * sin^2(pi x'/H) sin^2(pi y/H), x' = x - H: <U> = d/dy, <V> = -d/dx.
+    Above it a log law <U> = (u_tau / 0.41) ln(1 + (y - H)/z0), <V> = 0, driven by
+    grad<P> = (-1, 0) (zero in the cavity).  <omega> = min(1 + 10 d^(-1/2), 50) with d the
+    distance to the nearest no-slip wall; elliptic-relaxation tensor wp_diag * I;
+    Reynolds stresses r_diag * I.
+    """
+    H = mesh.meta.get("H", 1.0)
+    x, y = mesh.xy[:, 0], mesh.xy[:, 1]
+    n = mesh.n_nodes
+    above = y >= H
+    xp = x - H
+    k = math.pi / H
+    mu = np.zeros((n, 3))
+    mu[:, 0] = np.where(above, (u_tau / 0.41) * np.log1p(np.maximum(y - H, 0.0) / z0),
+                        recirc * np.sin(k * xp) ** 2 * k * np.sin(2 * k * y))
+    mu[:, 1] = np.where(above, 0.0, -recirc * k * np.sin(2 * k * xp) * np.sin(k * y) ** 2)
+    grad_p = np.zeros((n, 2))
+    grad_p[above, 0] = -1.0
+    wp = np.zeros((n, 6))
+    wp[:, 0:3] = wp_diag
+    d = _wall_distance_cavity(x, y, H)
+    with np.errstate(divide="ignore"):
+        om = np.where(d > 0, 1.0 + 10.0 / np.sqrt(np.maximum(d, 1e-300)), np.inf)
+    om = np.minimum(om, 50.0)
+    rey = np.zeros((n, 6))
+    rey[:, 0:3] = r_diag
+    return Fields(grad_p=grad_p, wp=wp, mean_u=mu, mean_omega=om, rey=rey)
+
+
+# ---------------------------------------------------------------------------------
 # named workloads
 # ---------------------------------------------------------------------------------
 
@@ -222,7 +396,32 @@ def channel_large(nx=400, ny=500, ppe=200, seed=MASTER_SEED):
     return mesh, channel_fields(mesh), model_constants(), init_desc(ppe=ppe, bins=(4, 2, 2))
 
 
+def cavity_small(nxh=20, ny_channel=20, ny_cavity=20, ppe=50, seed=MASTER_SEED):
+    """Street canyon for parity: 3 200 triangles, 50 particles per element, source at the
+    cavity centre."""
+    mesh = cavity_mesh(nxh, ny_channel, ny_cavity, seed=seed)
+    return mesh, cavity_fields(mesh), model_constants(), init_desc(ppe=ppe, bins=(4, 2, 2), src_x=1.5,
+                                                                     src_y=0.5)
+
+
+def cavity_large(nxh=250, ny_channel=500, ny_cavity=500, ppe=100, seed=MASTER_SEED):
+    """Street canyon at GPU scale: 1e6 triangles, 100 particles per element (1e8)."""
+    mesh = cavity_mesh(nxh, ny_channel, ny_cavity, seed=seed)
+    return mesh, cavity_fields(mesh), model_constants(), init_desc(ppe=ppe, bins=(4, 2, 2), src_x=1.5,
+                                                                     src_y=0.5)
+
+
+def cavity_huge(nxh=500, ny_channel=1000, ny_cavity=1000, ppe=120, seed=MASTER_SEED):
+    """Large street canyon: 4e6 triangles, 120 particles per element (4.8e8), 32 bins."""
+    mesh = cavity_mesh(nxh, ny_channel, ny_cavity, seed=seed)
+    return mesh, cavity_fields(mesh), model_constants(), init_desc(ppe=ppe, bins=(4, 4, 2), src_x=1.5,
+                                                                     src_y=0.5)
+
+
 WORKLOADS = {
     "channel_small": dict(fn=channel_small, dt=1e-3, steps=20, control=None),
     "channel_large": dict(fn=channel_large, dt=2e-4, steps=100, control=(150, 250)),
+    "cavity_small": dict(fn=cavity_small, dt=1e-4, steps=20, control=None),
+    "cavity_large": dict(fn=cavity_large, dt=1e-4, steps=200, control=None),
+    "cavity_huge": dict(fn=cavity_huge, dt=1e-4, steps=500, control=(90, 150)),
 }

@@ -244,3 +244,51 @@ def test_one_particle_bins_and_many_bins(gpu):
             ge.step(2e-3)
             rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
         compare_stats(ge.stats(), oe.stats(), _skip_nodes(mesh, excl))
+
+
+@pytest.mark.slow
+def test_channel_large_first_steps(gpu):
+    """The benchmark workload at full size (400 000 triangles, 8e7 particles), in the
+    benchmark's launch configuration (capacity 1.3 n0 + 1024, step + control(150, 250)):
+    control reports every step, every particle and every node after 3 steps."""
+    _say("test_channel_large_first_steps: channel 400x500, 200 per element")
+    mesh = W.channel_mesh(400, 500)
+    f = W.channel_fields(mesh)
+    mo = W.model_constants()
+    ini = W.init_desc(ppe=200, bins=(4, 2, 2))
+    n0 = mesh.n_elems * 200
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini, capacity=int(1.3 * n0) + 1024)
+    assert ge.count() == oe.count() == n0
+    for n in range(3):
+        oe.step(2e-4)
+        ge.step(2e-4)
+        ro, rg = oe.control(150, 250), ge.control(150, 250)
+        _say(f"  step {n + 1}: {rg}")
+        assert ro == {k: rg[k] for k in ro}, (ro, rg)
+    frame = og.export()["frame"]
+    rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh))
+    _say(f"  particles: {rep}")
+    assert len(excl) <= 8
+    compare_stats(ge.stats(), oe.stats(), _skip_nodes(mesh, excl))
+    assert ge.counters() == oe.counters()
+
+
+def test_cavity_small_parity(gpu):
+    """Street canyon (cavity corners, no-slip street level, free-slip top, periodic seam),
+    10 steps with number control every other step."""
+    _say("test_cavity_small_parity")
+    mesh, f, mo, ini = W.cavity_small()
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    excl = set()
+    for n in range(10):
+        oe.step(1e-3)
+        ge.step(1e-3)
+        if n % 2 == 1:
+            ro, rg = oe.control(40, 60), ge.control(40, 60)
+            assert ro == {k: rg[k] for k in ro}, (ro, rg)
+        rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+    compare_stats(ge.stats(), oe.stats(), _skip_nodes(mesh, excl))
+    c = ge.counters()
+    assert c["wall_a"] > 0 and c["reflections"] > 0 and c["source_hits"] > 0
+    assert c == oe.counters()
