@@ -19,6 +19,16 @@
  *      (Sec. 3.3).
  * Particle-number control (Sec. 3.7, App. B) is a separate call.
  *
+ * Two forms beyond the plain FP64 step:
+ *  - precision PDF_MIXED: velocity, frequency, scalar and weight are stored and advanced
+ *    in FP32 (nodal fields used by the particles in FP32, FP32 random-number mapping,
+ *    Kahan-compensated FP32 nodal sums); positions, the barycentric locate / reflect
+ *    tests and the final division of nodal sums by nodal weights stay FP64.
+ *  - several problems per ensemble: independent grids and particle sets (own seeds,
+ *    time steps, model constants, sources and bins) advanced together by the same
+ *    kernel launches; optionally every two steps replayed from a captured HIP graph
+ *    (pdf_set_options) with launch parameters chosen by pdf_autotune.
+ *
  * Conventions
  *  - Every call returns a pdf_status; 0 is success.  On failure pdf_last_error() returns
  *    a message for the calling thread.  No exception crosses the ABI.
@@ -54,6 +64,9 @@ typedef int32_t pdf_status;
 #define PDF_E_LOST (-6)      /* a particle could not be located after 64 moves */
 #define PDF_E_NONFINITE (-7) /* non-finite input field or particle state */
 #define PDF_E_STATE (-8)     /* call not valid in the current state */
+
+/* state precision of an ensemble (pdf_init_desc.precision) */
+enum { PDF_FP64 = 0, PDF_MIXED = 1 };
 
 /* boundary kinds of element edges; edge k of a triangle is the edge opposite vertex k */
 enum { PDF_EDGE_INTERIOR = 0, PDF_EDGE_WALL = 1, PDF_EDGE_SLIP = 2, PDF_EDGE_PERIODIC = 3 };
@@ -111,9 +124,11 @@ typedef struct {
  *  src_continuous 1: particles inside the disk after tracking get psi = 1 every step;
  *  bins[3]        requested velocity bins per direction (Sec. 3.5), each >= 1;
  *  min_per_bin    minimum particles per bin (>= 1; the paper uses 2);
- *  precision      0 (FP64 throughout);
- *  seed           seed of the counter-based generator;
- *  capacity       particle slots to allocate (0: 2 x ppe x n_elems). */
+ *  precision      PDF_FP64 or PDF_MIXED (the same for every problem of an ensemble);
+ *  seed           seed of the counter-based generator (key: seed low word, seed high
+ *                 word XOR the problem's index in the ensemble);
+ *  capacity       particle slots for this problem (0: max(2 x ppe x n_elems, 1024));
+ *                 the ensemble allocates the sum over its problems. */
 typedef struct {
     int32_t ppe;
     double u_sigma, omega_shape;
@@ -145,17 +160,20 @@ pdf_status pdf_grid_create(const pdf_mesh_desc* mesh, const pdf_fields_desc* fie
                            const pdf_model* model, void* hip_stream, pdf_grid* out);
 pdf_status pdf_grid_destroy(pdf_grid grid);
 
-/* Create an ensemble on grids[0] and seed ppe particles per element (Sec. 3.7): pid =
- * e * ppe + k; initial element-grouping, binning and statistics are computed.
- * n_problems must be 1.  Errors: PDF_E_INVAL, PDF_E_NOMEM, PDF_E_CAPACITY, PDF_E_HIP. */
+/* Create an ensemble of n_problems >= 1 independent problems, problem p on grids[p] with
+ * descs[p], and seed ppe particles per element (Sec. 3.7): pid = e * ppe + k within each
+ * problem; initial element-grouping, binning and statistics are computed.  The grids
+ * must outlive the ensemble.  Errors: PDF_E_INVAL, PDF_E_NOMEM, PDF_E_CAPACITY,
+ * PDF_E_HIP. */
 pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
                               int32_t n_problems, void* hip_stream, pdf_ens* out);
 pdf_status pdf_ens_destroy(pdf_ens ens);
 
-/* Advance n_steps time steps of size dt[0] (> 0).  Enqueues only; does not synchronise. */
+/* Advance n_steps time steps; problem p uses the time step dt[p] (> 0, one entry per
+ * problem).  Enqueues only; does not synchronise (a changed dt is uploaded first). */
 pdf_status pdf_step(pdf_ens ens, const double* dt, int32_t n_steps, void* hip_stream);
 
-/* Nodal statistics of the last step (Sec. 3.3), out = [n_nodes][13]:
+/* Nodal statistics of the last step (Sec. 3.3) of one problem, out = [n_nodes][13]:
  *   W = sum_p w_p N_n(x_p), <U1>, <U2>, <U3>, <omega>, <psi>,
  *   <u1u1>, <u2u2>, <u3u3>, <u1u2>, <u1u3>, <u2u3>, <psi'psi'>
  * over the particles of the elements around node n, weighted by w_p N_n(x_p); the
@@ -175,27 +193,31 @@ pdf_status pdf_stats(pdf_ens ens, int32_t problem, double* out, int32_t out_is_d
 pdf_status pdf_control(pdf_ens ens, int32_t n_min, int32_t n_max, pdf_control_report* report,
                        void* hip_stream);
 
-/* Live particles (synchronises). */
+/* Live particles of one problem, or of the whole ensemble for problem = -1
+ * (synchronises). */
 pdf_status pdf_count(pdf_ens ens, int32_t problem, int64_t* live);
 
-/* Copy the live particles to host arrays of at least cap entries (any pointer may be
- * NULL): x, y, u [n][3], omega, psi, weight, pid, host element.  *n_out = live count.
- * Order: element-grouped, canonical within elements after a step.  Synchronises. */
+/* Copy the live particles of one problem to host arrays of at least cap entries (any
+ * pointer may be NULL): x, y, u [n][3], omega, psi, weight, pid, host element (numbered
+ * within the problem's grid).  *n_out = live count.  Order: element-grouped, canonical
+ * within elements after a step.  Mixed-form values are widened to double.  Synchronises. */
 pdf_status pdf_particles_export(pdf_ens ens, int32_t problem, int64_t cap, double* x, double* y,
                                 double* u, double* omega, double* psi, double* w,
                                 uint64_t* pid, int32_t* elem, int64_t* n_out, void* hip_stream);
 
 /* Replace the particle state with n host-side particles (elem must be each particle's host
  * element); sets the step counter and the next pid, then recomputes grouping, bins and
- * statistics without mixing.  Synchronises.  Errors: PDF_E_INVAL, PDF_E_CAPACITY. */
+ * statistics without mixing.  Single-problem ensembles only (problem 0); mixed-form
+ * ensembles round the values to FP32.  Synchronises.  Errors: PDF_E_INVAL,
+ * PDF_E_CAPACITY, PDF_E_NONFINITE. */
 pdf_status pdf_particles_import(pdf_ens ens, int32_t problem, int64_t n, const double* x,
                                 const double* y, const double* u, const double* omega,
                                 const double* psi, const double* w, const uint64_t* pid,
                                 const int32_t* elem, int64_t step, uint64_t next_pid,
                                 void* hip_stream);
 
-/* Event counters since set-up (synchronises): wall (a), wall (b), reflections, fall-back
- * searches, omega reflections, C0 clamps, walk moves, source hits. */
+/* Event counters of one problem since set-up (synchronises): wall (a), wall (b),
+ * reflections, fall-back searches, omega reflections, C0 clamps, walk moves, source hits. */
 pdf_status pdf_counters(pdf_ens ens, int32_t problem, int64_t out[PDF_NCOUNTERS]);
 
 /* Kernel timing with HIP events on the ensemble's stream.  enable = 1 starts (and resets)
@@ -204,6 +226,31 @@ pdf_status pdf_counters(pdf_ens ens, int32_t problem, int64_t out[PDF_NCOUNTERS]
  * scatter, element pass, node finalize, control plan, control scan, control apply, fill,
  * count, other.  Synchronises when reading. */
 pdf_status pdf_timing(pdf_ens ens, int32_t enable, double* ms_out, int64_t* launches_out);
+
+/* Launch options of an ensemble; none changes any result.
+ *  use_graph  1: pdf_step replays every two steps from a captured HIP graph on a
+ *             stream of the ensemble (ordered after and before hip_stream by events),
+ *             captured again when the slot bound or a time step changes;
+ *  adv_block  workgroup size of the particle loop: 64, 128 or 256;
+ *  ppl        particles per lane of the wavefront element kernel (elements with more
+ *             than 64 x ppl particles take the workgroup kernel): 1..6 or 8. */
+typedef struct {
+    int32_t use_graph;
+    int32_t adv_block;
+    int32_t ppl;
+} pdf_options;
+
+pdf_status pdf_get_options(pdf_ens ens, pdf_options* out);
+/* Errors: PDF_E_INVAL for values outside the lists above.  Synchronises. */
+pdf_status pdf_set_options(pdf_ens ens, const pdf_options* opt);
+
+/* Autotuner: times candidate (adv_block, ppl) pairs on the live ensemble, each for one
+ * warm-up step plus steps_per_trial steps, and keeps the fastest.  The ensemble really
+ * advances by all these steps (results do not depend on the options).  trial_ms, when
+ * not NULL, receives up to *n_trials timings; *n_trials returns the number of trials.
+ * Synchronises. */
+pdf_status pdf_autotune(pdf_ens ens, const double* dt, int32_t steps_per_trial, void* hip_stream,
+                        pdf_options* chosen, int32_t* n_trials, double* trial_ms);
 
 /* Wait for the ensemble's work and return its sticky device error, if any. */
 pdf_status pdf_sync(pdf_ens ens);

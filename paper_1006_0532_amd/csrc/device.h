@@ -129,26 +129,78 @@ __host__ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, doub
     z1 = r * s;
 }
 
+// ------------------------------------------------------------------------------------
+// mixed form: the same Philox words mapped in FP32
+// ------------------------------------------------------------------------------------
+// uniform on (0, 1) from the top 24 bits: ((w >> 8) + 1/2) * 2^-24, exact in float
+__device__ __forceinline__ float u01f(uint32_t w) { return ((float)(w >> 8) + 0.5f) * 5.9604644775390625e-8f; }
+
+__device__ __forceinline__ void box_muller_f(uint32_t a, uint32_t b, float& z0, float& z1)
+{
+    const float r = sqrtf(-2.0f * logf(u01f(a)));
+    float s, c;
+    sincospif(2.0f * u01f(b), &s, &c);   // sin, cos of 2 pi u; 2u is exact
+    z0 = r * c;
+    z1 = r * s;
+}
+
+// precision-generic wrappers: R = double (FP64 form) or float (mixed form)
+template <class R> struct RMath;
+template <> struct RMath<double> {
+    __device__ static double uni(uint32_t w) { return u01(w); }
+    __device__ static void normal2(uint32_t a, uint32_t b, double& z0, double& z1) { box_muller(a, b, z0, z1); }
+    __device__ static double sqrt_(double v) { return sqrt(v); }
+    __device__ static double log_(double v) { return log(v); }
+    __device__ static double exp_(double v) { return exp(v); }
+};
+template <> struct RMath<float> {
+    __device__ static float uni(uint32_t w) { return u01f(w); }
+    __device__ static void normal2(uint32_t a, uint32_t b, float& z0, float& z1) { box_muller_f(a, b, z0, z1); }
+    __device__ static float sqrt_(float v) { return sqrtf(v); }
+    __device__ static float log_(float v) { return logf(v); }
+    __device__ static float exp_(float v) { return expf(v); }
+};
+
 // Gamma(shape >= 1) with the given mean, Marsaglia & Tsang (ACM TOMS 2000): attempt a
 // draws from counter index a; after 16 rejected attempts the mean is returned.
-__device__ __noinline__ double gamma_draw(double shape, double mean, RngKey key, uint64_t pid, uint32_t step,
-                                          uint32_t tag)
+template <class R>
+__device__ __noinline__ R gamma_draw(R shape, R mean, RngKey key, uint64_t pid, uint32_t step, uint32_t tag)
 {
-    const double d = shape - 1.0 / 3.0;
-    const double c = 1.0 / sqrt(9.0 * d);
+    using M = RMath<R>;
+    const R d = shape - R(1) / R(3);
+    const R c = R(1) / M::sqrt_(R(9) * d);
     for (uint32_t a = 0; a < 16u; ++a) {
         const Words4 w = rng_draw(key, pid, step, tag, a);
-        double x, unused;
-        box_muller(w.w0, w.w1, x, unused);
-        const double u = u01(w.w2);
-        double v = 1.0 + c * x;
-        if (v <= 0.0) continue;
+        R x, unused;
+        M::normal2(w.w0, w.w1, x, unused);
+        const R u = M::uni(w.w2);
+        R v = R(1) + c * x;
+        if (v <= R(0)) continue;
         v = v * v * v;
-        if (u < 1.0 - 0.0331 * (x * x) * (x * x)) return d * v * (mean / shape);
-        if (log(u) < 0.5 * x * x + d * (1.0 - v + log(v))) return d * v * (mean / shape);
+        if (u < R(1) - R(0.0331) * (x * x) * (x * x)) return d * v * (mean / shape);
+        if (M::log_(u) < R(0.5) * x * x + d * (R(1) - v + M::log_(v))) return d * v * (mean / shape);
     }
     return mean;
 }
+
+// Running sum: plain in FP64; Kahan-compensated in FP32 (mixed form)
+template <class R> struct Acc;
+template <> struct Acc<double> {
+    double s = 0.0;
+    __device__ void add(double v) { s += v; }
+    __device__ double value() const { return s; }
+};
+template <> struct Acc<float> {
+    float s = 0.0f, c = 0.0f;
+    __device__ void add(float v)
+    {
+        const float y = v - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ float value() const { return s - c; }
+};
 
 // ------------------------------------------------------------------------------------
 // P1 triangle geometry (Eqs. 37-38, 44-45)
@@ -199,5 +251,26 @@ __device__ __forceinline__ double wave_sum_double(double v)
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
+
+// FP32 butterfly sum carrying the rounding error of every addition (two-sum), so the
+// result is as accurate as a sum in twice the precision
+__device__ __forceinline__ float wave_sum_comp(float v)
+{
+    float c = 0.0f;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const float w = __shfl_xor(v, o), cw = __shfl_xor(c, o);
+        const float s = v + w;
+        const float bb = s - v;
+        const float e = (v - (s - bb)) + (w - bb);
+        v = s;
+        c = c + cw + e;
+    }
+    return v + c;
+}
+
+template <class R> __device__ __forceinline__ R wave_sum_real(R v);
+template <> __device__ __forceinline__ double wave_sum_real<double>(double v) { return wave_sum_double(v); }
+template <> __device__ __forceinline__ float wave_sum_real<float>(float v) { return wave_sum_comp(v); }
 
 }  // namespace pdfgpu

@@ -1,4 +1,13 @@
 // Kernel argument blocks and launchers of libpdfgpu.
+//
+// Every particle kernel is instantiated for the two forms of the state:
+//   R = double  FP64 form: everything in FP64;
+//   R = float   mixed form: velocity, frequency, scalar and weight (and their updates,
+//               the nodal fields they use and the nodal sums) in FP32; positions, the
+//               barycentric locate / reflect tests and the final nodal division in FP64.
+// An ensemble may hold several independent problems (the batched form): their grids are
+// concatenated, every element record carries its problem index, and per-problem
+// parameters sit in a small device table.
 #pragma once
 #include "pdf_impl.h"
 
@@ -8,38 +17,35 @@ constexpr int EP_NT = 256;      // threads per element in the element pass
 constexpr int MAXBINS = 1024;   // upper bound of bins[0]*bins[1]*bins[2]
 constexpr int EP_BIG_BLOCKS = 512;  // workgroups of the large-element pass
 
+template <class R>
 struct AdvanceArgs {
-    Soa s;
+    SoaT<R> s;
     const ElemGeo* geo;
-    const double* node;
+    const R* node;              // [nn][NODE_STRIDE] in the state's precision
     const int64_t* n2e_ptr;
     const int32_t* n2e;
     int32_t* counts;
     uint32_t* err;
-    unsigned long long* cnt;
-    const int64_t* nslots;
+    unsigned long long* cnt;    // [problem][NCOUNT][CNT_SLOTS]
+    const int64_t* meta;        // [0] used slots, [4] step counter
     int64_t ne;
-    double period;
-    ModelC m;
-    double dt;
-    RngKey key;
-    uint32_t step;
-    double src_x, src_y, src_r2;
-    int32_t src_cont;
+    ProbParams p0;              // parameters of problem 0 (single-problem ensembles)
+    const ProbParams* prm;      // [n_problems] (batched ensembles)
 };
 
+template <class R>
 struct ElementArgs {
-    Soa in, out;
+    SoaT<R> in, out;
     const int32_t* start;
     const int32_t* idx;
     const ElemGeo* geo;
-    const double* shift;
-    double* part;
+    const ProbParams* prm;
+    const R* shift;
+    R* part;
     const double* tm;
-    double dt;
+    int32_t mix;          // 0: binning and statistics only (set-up, import)
     int64_t ne;
     int64_t cap;
-    int32_t bins0, bins1, bins2, minpb;
     int32_t lds_max;
     int32_t ppl;          // particles per lane of the wavefront kernel (1..6, 8)
     int32_t* big_list;    // [ne] elements left to the workgroup kernel
@@ -49,34 +55,38 @@ struct ElementArgs {
     double* gu3;
 };
 
+template <class R>
 struct NodeArgs {
-    const double* part;
+    const R* part;
     const int64_t* n2e_ptr;
     const int32_t* n2e;
-    double* shift;
+    R* shift;
     double* stats;
     int64_t nn;
     const int32_t* start;
     int64_t ne;
     int64_t* meta;
     int32_t* big_count;
+    int32_t advance_step;   // 1 after a time step: the device step counter moves on
 };
 
+template <class R>
 struct InitArgs {
-    Soa s;
+    SoaT<R> s;
     const ElemGeo* geo;
-    const double* node;
+    const R* node;
+    const ProbParams* prm;
+    int32_t n_problems;
     int64_t n;
-    int32_t ppe;
-    RngKey key;
-    double u_sigma, omega_shape;
-    double src_x, src_y, src_r2;
-    double period;
 };
 
+template <class R>
 struct ControlArgs {
-    Soa s;
+    SoaT<R> s;
     const int32_t* start;
+    const ElemGeo* geo;
+    ProbParams* prm;
+    int32_t n_problems;
     int32_t* clone;
     const int32_t* off;
     unsigned long long* rep;
@@ -84,32 +94,43 @@ struct ControlArgs {
     const int64_t* nslots;
     int64_t ne, cap;
     int32_t n_min, n_max;
-    int32_t bins0, bins1, bins2, minpb;
-    uint64_t next_pid;
 };
 
-void launch_advance(const AdvanceArgs& a, int64_t n_ub, hipStream_t s);
+template <class R>
+void launch_advance(const AdvanceArgs<R>& a, int64_t n_ub, bool batched, int block, hipStream_t s);
+template <class R>
+void launch_element_pass(const ElementArgs<R>& a, hipStream_t s);
+template <class R>
+hipError_t prepare_element_pass(int lds_max);
+template <class R>
+size_t element_pass_smem(int lds_max);
+template <class R>
+void launch_node_finalize(const NodeArgs<R>& a, hipStream_t s);
+template <class R>
+void launch_init(const InitArgs<R>& a, hipStream_t s);
+template <class R>
+void launch_ctl_plan(const ControlArgs<R>& a, hipStream_t s);
+template <class R>
+void launch_ctl_apply(const ControlArgs<R>& a, hipStream_t s);
+template <class R>
+void launch_shift_init(const R* node, int64_t nn, R* shift, hipStream_t s);
+
 void launch_count(const int32_t* elem, const int64_t* nslots, int64_t n_ub, int64_t ne, int32_t* counts,
                   uint32_t* err, hipStream_t s);
+void launch_count_range(const int32_t* elem, const int64_t* nslots, int64_t n_ub, int32_t lo, int32_t hi,
+                        unsigned long long* out, hipStream_t s);
 int64_t scan_blocks(int64_t n);
 int64_t scan_max_elems();
 void launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* tmp, hipStream_t s);
 void launch_scatter(const int32_t* elem, const int64_t* nslots, int64_t n_ub, int64_t ne, int32_t* counts,
                     const int32_t* start, int32_t* idx, uint32_t* err, hipStream_t s);
-hipError_t prepare_element_pass(int lds_max);
-size_t element_pass_smem(int lds_max);
-void launch_element_pass(const ElementArgs& a, hipStream_t s);
-void launch_node_finalize(const NodeArgs& a, hipStream_t s);
-void launch_init(const InitArgs& a, hipStream_t s);
-void launch_tm(const ElemGeo* geo, const double* node, int64_t ne, ModelC m, double sx, double sy, double sr,
-               double period, double* tm, hipStream_t s);
-void launch_ctl_plan(const ControlArgs& a, hipStream_t s);
-void launch_ctl_apply(const ControlArgs& a, hipStream_t s);
+void launch_tm(const ElemGeo* geo, const double* node, int64_t ne, const ProbParams* prm, double* tm,
+               hipStream_t s);
 void launch_ctl_finish(int64_t* meta, const int32_t* off, int64_t ne, const unsigned long long* rep, int64_t cap,
-                       hipStream_t s);
+                       ProbParams* prm, int32_t n_problems, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
-void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
-void launch_shift_init(const double* node, int64_t nn, double* shift, hipStream_t s);
+void launch_f64_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
+void launch_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s);
 
 }  // namespace pdfgpu

@@ -9,6 +9,8 @@
 //                  particles in canonical order into the other state buffer
 //   k_node_finalize per node: fixed-order sum of the vertex partials -> statistics
 // and number control is k_ctl_plan (merges), a scan, and k_ctl_apply (splits).
+// The particle kernels are templates on the state precision R (double: FP64 form, float:
+// mixed form); the particle loop also on whether the ensemble holds several problems.
 #include "device.h"
 #include "kernels.h"
 
@@ -50,53 +52,61 @@ struct AdvEvents {
     int ev_a, ev_b, omrefl, clamp, src, steps, refl, fb;
 };
 
-// one particle of the particle loop: returns its new host element (its old one when it
-// could not be tracked)
-__device__ __forceinline__ int32_t advance_one(const AdvanceArgs& a, const int64_t i, const int32_t e, AdvEvents& ev)
+// One particle of the particle loop.  Returns its new host element (its old one when it
+// could not be tracked) and the particle's problem in prob.  R = double: FP64 throughout;
+// R = float: velocity, frequency and their SDEs in FP32, positions and tracking in FP64.
+template <class R, bool BATCHED>
+__device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const int64_t i, const int32_t e,
+                                               const uint32_t step, AdvEvents& ev, int& prob)
 {
-    const ModelC& m = a.m;
+    using M = RMath<R>;
     const ElemGeo* G = a.geo + e;
+    const ProbParams& P = BATCHED ? a.prm[G->prob] : a.p0;
+    prob = BATCHED ? G->prob : 0;
+    const R nu = (R)P.m.nu, rho = (R)P.m.rho, C3 = (R)P.m.C3, C4 = (R)P.m.C4, CT = (R)P.m.CT,
+            Cw1 = (R)P.m.Cw1, Cw2 = (R)P.m.Cw2;
+    const R dt = (R)P.dt;
     const double x0 = a.s.x[i], y0 = a.s.y[i];
-    const double u0 = a.s.u0[i], u1 = a.s.u1[i], u2 = a.s.u2[i];
-    const double om = a.s.om[i];
+    const R u0 = a.s.u0[i], u1 = a.s.u1[i], u2 = a.s.u2[i];
+    const R om = a.s.om[i];
     const uint64_t pid = a.s.pid[i];
 
-    // (a1) P1 interpolation of the nodal fields (Eq. 37)
+    // (a1) P1 interpolation of the nodal fields (Eq. 37); area coordinates in FP64
     double na, nb, nc;
     area_coords(G, x0, y0, na, nb, nc);
     const double ia = 1.0 / G->area;
-    const double la = na * ia, lb = nb * ia, lc = nc * ia;
-    const double* __restrict__ FA = a.node + (int64_t)G->node[0] * NODE_STRIDE;
-    const double* __restrict__ FB = a.node + (int64_t)G->node[1] * NODE_STRIDE;
-    const double* __restrict__ FC = a.node + (int64_t)G->node[2] * NODE_STRIDE;
+    const R la = (R)(na * ia), lb = (R)(nb * ia), lc = (R)(nc * ia);
+    const R* __restrict__ FA = a.node + (int64_t)G->node[0] * NODE_STRIDE;
+    const R* __restrict__ FB = a.node + (int64_t)G->node[1] * NODE_STRIDE;
+    const R* __restrict__ FC = a.node + (int64_t)G->node[2] * NODE_STRIDE;
     // interpolation in three groups of fields; the empty asm statements keep the
     // compiler from hoisting all 63 node loads at once (register pressure)
     auto ip = [&](int q) { return la * FA[q] + lb * FB[q] + lc * FC[q]; };
-    const double gu0 = G->gu[0], gu1 = G->gu[1], gu2 = G->gu[2], gu3 = G->gu[3], gu4 = G->gu[4],
-                 gu5 = G->gu[5];
+    const R gu0 = (R)G->gu[0], gu1 = (R)G->gu[1], gu2 = (R)G->gu[2], gu3 = (R)G->gu[3], gu4 = (R)G->gu[4],
+            gu5 = (R)G->gu[5];
 
     // (a2) closure (Eqs. 11, 18, 20)
-    const double R11 = ip(NF_RE), R22 = ip(NF_RE + 1), R33 = ip(NF_RE + 2);
-    const double R12 = ip(NF_RE + 3), R13 = ip(NF_RE + 4), R23 = ip(NF_RE + 5);
-    const double Om = ip(NF_OM);
+    const R R11 = ip(NF_RE), R22 = ip(NF_RE + 1), R33 = ip(NF_RE + 2);
+    const R R12 = ip(NF_RE + 3), R13 = ip(NF_RE + 4), R23 = ip(NF_RE + 5);
+    const R Om = ip(NF_OM);
     asm volatile("" ::: "memory");
-    const double k = 0.5 * (R11 + R22 + R33);
-    const double eps = Om * (k + m.nu * m.CT * m.CT * Om);
-    const double prod = -(R11 * gu0 + R12 * gu1 + R12 * gu2 + R22 * gu3 + R13 * gu4 + R23 * gu5);
-    const double W11 = ip(NF_WP), W22 = ip(NF_WP + 1), W33 = ip(NF_WP + 2);
-    const double W12 = ip(NF_WP + 3), W13 = ip(NF_WP + 4), W23 = ip(NF_WP + 5);
+    const R k = R(0.5) * (R11 + R22 + R33);
+    const R eps = Om * (k + nu * CT * CT * Om);
+    const R prod = -(R11 * gu0 + R12 * gu1 + R12 * gu2 + R22 * gu3 + R13 * gu4 + R23 * gu5);
+    const R W11 = ip(NF_WP), W22 = ip(NF_WP + 1), W33 = ip(NF_WP + 2);
+    const R W12 = ip(NF_WP + 3), W13 = ip(NF_WP + 4), W23 = ip(NF_WP + 5);
     asm volatile("" ::: "memory");
-    const double wpR = W11 * R11 + W22 * R22 + W33 * R33 + 2.0 * (W12 * R12 + W13 * R13 + W23 * R23);
-    double c0eps = -2.0 * wpR / (3.0 * k);
-    if (c0eps < 0.0) {
-        c0eps = 0.0;
+    const R wpR = W11 * R11 + W22 * R22 + W33 * R33 + R(2) * (W12 * R12 + W13 * R13 + W23 * R23);
+    R c0eps = -R(2) * wpR / (R(3) * k);
+    if (c0eps < R(0)) {
+        c0eps = R(0);
         ev.clamp = 1;
     }
-    const double Sw = m.Cw2 - m.Cw1 * prod / eps;
-    const double ik = 1.0 / k;
-    const double G11 = (W11 - 0.5 * eps) * ik, G22 = (W22 - 0.5 * eps) * ik, G33 = (W33 - 0.5 * eps) * ik;
-    const double G12 = W12 * ik, G13 = W13 * ik, G23 = W23 * ik;
-    double f[21];
+    const R Sw = Cw2 - Cw1 * prod / eps;
+    const R ik = R(1) / k;
+    const R G11 = (W11 - R(0.5) * eps) * ik, G22 = (W22 - R(0.5) * eps) * ik, G33 = (W33 - R(0.5) * eps) * ik;
+    const R G12 = W12 * ik, G13 = W13 * ik, G23 = W23 * ik;
+    R f[21];
     f[NF_MU] = ip(NF_MU);
     f[NF_MU + 1] = ip(NF_MU + 1);
     f[NF_MU + 2] = ip(NF_MU + 2);
@@ -108,38 +118,44 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs& a, const int64
     asm volatile("" ::: "memory");
 
     // random numbers: 6 Gaussians and one uniform (Sec. 3.9)
-    const Words4 wA = rng_draw(a.key, pid, a.step, TAG_STEP, 0);
-    const Words4 wB = rng_draw(a.key, pid, a.step, TAG_STEP, 1);
-    double z0, z1, z2, z3, z4, z5;
-    box_muller(wA.w0, wA.w1, z0, z1);
-    box_muller(wA.w2, wA.w3, z2, z3);
-    box_muller(wB.w0, wB.w1, z4, z5);
-    const double sdt = sqrt(a.dt);
-    const double dWx = sdt * z0, dWy = sdt * z1;
-    const double dWp0 = sdt * z2, dWp1 = sdt * z3, dWp2 = sdt * z4, dWo = sdt * z5;
-    const double eta = u01(wB.w2);
-    const double s2nu = sqrt(2.0 * m.nu);
-    const double sc0 = sqrt(c0eps);
+    const Words4 wA = rng_draw(P.key, pid, step, TAG_STEP, 0);
+    const Words4 wB = rng_draw(P.key, pid, step, TAG_STEP, 1);
+    R z0, z1, z2, z3, z4, z5;
+    M::normal2(wA.w0, wA.w1, z0, z1);
+    M::normal2(wA.w2, wA.w3, z2, z3);
+    M::normal2(wB.w0, wB.w1, z4, z5);
+    const R sdt = M::sqrt_(dt);
+    const R dWx = sdt * z0, dWy = sdt * z1;
+    const R dWp0 = sdt * z2, dWp1 = sdt * z3, dWp2 = sdt * z4, dWo = sdt * z5;
+    const R eta = M::uni(wB.w2);
+    const R s2nu = M::sqrt_(R(2) * nu);
+    const R sc0 = M::sqrt_(c0eps);
 
     // velocity, Eq. (27)
-    const double d0 = u0 - f[NF_MU], d1 = u1 - f[NF_MU + 1], d2 = u2 - f[NF_MU + 2];
-    const double irho = 1.0 / m.rho;
-    const double dr0 = -f[NF_GP] * irho + 2.0 * m.nu * f[NF_LAP] + G11 * d0 + G12 * d1 + G13 * d2;
-    const double dr1 = -f[NF_GP + 1] * irho + 2.0 * m.nu * f[NF_LAP + 1] + G12 * d0 + G22 * d1 + G23 * d2;
-    const double dr2 = 2.0 * m.nu * f[NF_LAP + 2] + G13 * d0 + G23 * d1 + G33 * d2;
-    double v0 = u0 + dr0 * a.dt + s2nu * (gu0 * dWx + gu1 * dWy) + sc0 * dWp0;
-    double v1 = u1 + dr1 * a.dt + s2nu * (gu2 * dWx + gu3 * dWy) + sc0 * dWp1;
-    double v2 = u2 + dr2 * a.dt + s2nu * (gu4 * dWx + gu5 * dWy) + sc0 * dWp2;
+    const R d0 = u0 - f[NF_MU], d1 = u1 - f[NF_MU + 1], d2 = u2 - f[NF_MU + 2];
+    const R irho = R(1) / rho;
+    const R dr0 = -f[NF_GP] * irho + R(2) * nu * f[NF_LAP] + G11 * d0 + G12 * d1 + G13 * d2;
+    const R dr1 = -f[NF_GP + 1] * irho + R(2) * nu * f[NF_LAP + 1] + G12 * d0 + G22 * d1 + G23 * d2;
+    const R dr2 = R(2) * nu * f[NF_LAP + 2] + G13 * d0 + G23 * d1 + G33 * d2;
+    R v0 = u0 + dr0 * dt + s2nu * (gu0 * dWx + gu1 * dWy) + sc0 * dWp0;
+    R v1 = u1 + dr1 * dt + s2nu * (gu2 * dWx + gu3 * dWy) + sc0 * dWp1;
+    R v2 = u2 + dr2 * dt + s2nu * (gu4 * dWx + gu5 * dWy) + sc0 * dWp2;
     // frequency, Eq. (19): |omega| in the diffusion, reflected at zero
-    double omn = om - m.C3 * Om * (om - Om) * a.dt - Sw * Om * om * a.dt +
-                 sqrt(2.0 * m.C3 * m.C4 * Om * Om * fabs(om)) * dWo;
-    if (omn < 0.0) {
+    const R aom = om < R(0) ? -om : om;
+    R omn = om - C3 * Om * (om - Om) * dt - Sw * Om * om * dt + M::sqrt_(R(2) * C3 * C4 * Om * Om * aom) * dWo;
+    if (omn < R(0)) {
         omn = -omn;
         ev.omrefl = 1;
     }
-    // position, Eq. (7), with the start-of-step velocity
-    double x = x0 + u0 * a.dt + s2nu * dWx;
-    double y = y0 + u1 * a.dt + s2nu * dWy;
+    // position, Eq. (7), with the start-of-step velocity (always accumulated in FP64)
+    double x, y;
+    if constexpr (sizeof(R) == sizeof(double)) {
+        x = x0 + u0 * P.dt + s2nu * dWx;
+        y = y0 + u1 * P.dt + s2nu * dWy;
+    } else {
+        x = x0 + (double)(u0 * dt + s2nu * dWx);
+        y = y0 + (double)(u1 * dt + s2nu * dWy);
+    }
 
     // (a3) next-best-element walk (Sec. 3.6) with particle wall conditions (Sec. 3.8)
     int32_t c = e;
@@ -196,73 +212,69 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs& a, const int64
         if (kd == KIND_WALL) {
             wall_a = 1;
         } else {
-            const double un = v0 * nx + v1 * ny;
-            v0 = v0 - 2.0 * un * nx;
-            v1 = v1 - 2.0 * un * ny;
+            const R rnx = (R)nx, rny = (R)ny;
+            const R un = v0 * rnx + v1 * rny;
+            v0 = v0 - R(2) * un * rnx;
+            v1 = v1 - R(2) * un * rny;
         }
         ++ev.refl;
     }
     if (!found) {
         atomicOr(a.err, ERR_LOST);
         return e;   // the particle keeps its start-of-step state
-    } else {
-        // no-slip events: (a) crossed the wall; (b) Eq. (53) in wall elements
-        bool hit = wall_a != 0;
-        const ElemGeo* C = a.geo + c;
-        if (!hit && C->wall && m.nu * a.dt > 0.0) {
-            double dn = (x0 + shift - C->wl[0]) * C->wl[2] + (y0 - C->wl[1]) * C->wl[3];
-            double dn1 = (x - C->wl[0]) * C->wl[2] + (y - C->wl[1]) * C->wl[3];
-            dn = dn < 0.0 ? 0.0 : dn;
-            dn1 = dn1 < 0.0 ? 0.0 : dn1;
-            const double fw = exp(-dn * dn1 / (m.nu * a.dt));
-            if (eta < fw) {
-                hit = true;
-                ev.ev_b = 1;
-            }
-        }
-        if (hit) {
-            ev.ev_a = wall_a;
-            double pa_, pb_, pc_;
-            area_coords(C, x, y, pa_, pb_, pc_);
-            const double* __restrict__ HA = a.node + (int64_t)C->node[0] * NODE_STRIDE;
-            const double* __restrict__ HB = a.node + (int64_t)C->node[1] * NODE_STRIDE;
-            const double* __restrict__ HC = a.node + (int64_t)C->node[2] * NODE_STRIDE;
-            const double omw = (pa_ / C->area) * HA[NF_OM] + (pb_ / C->area) * HB[NF_OM] +
-                               (pc_ / C->area) * HC[NF_OM];
-            v0 = v1 = v2 = 0.0;
-            omn = gamma_draw(1.0 / m.C4, omw, a.key, pid, a.step, TAG_WALL_GAMMA);
-        }
-        a.s.x[i] = x;
-        a.s.y[i] = y;
-        a.s.u0[i] = v0;
-        a.s.u1[i] = v1;
-        a.s.u2[i] = v2;
-        a.s.om[i] = omn;
-        a.s.elem[i] = c;
-        if (a.src_cont) {
-            double dx = x - a.src_x, dy = y - a.src_y;
-            if (a.period > 0.0) {
-                if (dx > 0.5 * a.period) dx -= a.period;
-                else if (dx < -0.5 * a.period) dx += a.period;
-            }
-            if (dx * dx + dy * dy < a.src_r2) {
-                a.s.psi[i] = 1.0;
-                ev.src = 1;
-            }
-        }
-        if (!(isfinite(x) && isfinite(y) && isfinite(v0) && isfinite(v1) && isfinite(v2) && isfinite(omn)))
-            atomicOr(a.err, ERR_NONFINITE);
-        return c;
     }
+    // no-slip events: (a) crossed the wall; (b) Eq. (53) in wall elements
+    bool hit = wall_a != 0;
+    const ElemGeo* C = a.geo + c;
+    if (!hit && C->wall && P.m.nu * P.dt > 0.0) {
+        double dn = (x0 + shift - C->wl[0]) * C->wl[2] + (y0 - C->wl[1]) * C->wl[3];
+        double dn1 = (x - C->wl[0]) * C->wl[2] + (y - C->wl[1]) * C->wl[3];
+        dn = dn < 0.0 ? 0.0 : dn;
+        dn1 = dn1 < 0.0 ? 0.0 : dn1;
+        const R fw = M::exp_((R)(-dn * dn1 / (P.m.nu * P.dt)));
+        if (eta < fw) {
+            hit = true;
+            ev.ev_b = 1;
+        }
+    }
+    if (hit) {
+        ev.ev_a = wall_a;
+        double pa_, pb_, pc_;
+        area_coords(C, x, y, pa_, pb_, pc_);
+        const R* __restrict__ HA = a.node + (int64_t)C->node[0] * NODE_STRIDE;
+        const R* __restrict__ HB = a.node + (int64_t)C->node[1] * NODE_STRIDE;
+        const R* __restrict__ HC = a.node + (int64_t)C->node[2] * NODE_STRIDE;
+        const R omw = (R)(pa_ / C->area) * HA[NF_OM] + (R)(pb_ / C->area) * HB[NF_OM] +
+                      (R)(pc_ / C->area) * HC[NF_OM];
+        v0 = v1 = v2 = R(0);
+        omn = gamma_draw<R>(R(1) / C4, omw, P.key, pid, step, TAG_WALL_GAMMA);
+    }
+    a.s.x[i] = x;
+    a.s.y[i] = y;
+    a.s.u0[i] = v0;
+    a.s.u1[i] = v1;
+    a.s.u2[i] = v2;
+    a.s.om[i] = omn;
+    a.s.elem[i] = c;
+    if (P.src_cont) {
+        double dx = x - P.src_x, dy = y - P.src_y;
+        if (P.period > 0.0) {
+            if (dx > 0.5 * P.period) dx -= P.period;
+            else if (dx < -0.5 * P.period) dx += P.period;
+        }
+        if (dx * dx + dy * dy < P.src_r2) {
+            a.s.psi[i] = R(1);
+            ev.src = 1;
+        }
+    }
+    if (!(isfinite(x) && isfinite(y) && isfinite(v0) && isfinite(v1) && isfinite(v2) && isfinite(omn)))
+        atomicOr(a.err, ERR_NONFINITE);
+    return c;
 }
 
-// event counters: wavefront sums, then one workgroup sum per counter added to one of
-// CNT_SLOTS spread copies (no single hot address)
-__device__ __forceinline__ void flush_events(const AdvanceArgs& a, const AdvEvents& ev)
+// event counters of one wavefront: counts of flagged lanes and sums of the walk counts
+__device__ __forceinline__ void wave_events(const AdvEvents& ev, int v[NCOUNT])
 {
-    const int lane = lane_id(), wid = threadIdx.x >> 6;
-    __shared__ int wsum[4][NCOUNT];
-    int v[NCOUNT];
     v[0] = __popcll(__ballot(ev.ev_a != 0));
     v[1] = __popcll(__ballot(ev.ev_b != 0));
     v[4] = __popcll(__ballot(ev.omrefl != 0));
@@ -274,30 +286,65 @@ __device__ __forceinline__ void flush_events(const AdvanceArgs& a, const AdvEven
         v[2] = wave_sum_int(ev.refl);
         v[3] = wave_sum_int(ev.fb);
     }
-    if (lane == 0)
-        for (int q = 0; q < NCOUNT; ++q) wsum[wid][q] = v[q];
-    __syncthreads();
-    if (threadIdx.x < NCOUNT) {
-        const int q = threadIdx.x;
-        const int tot = wsum[0][q] + wsum[1][q] + wsum[2][q] + wsum[3][q];
-        if (tot) atomicAdd(a.cnt + q * CNT_SLOTS + (blockIdx.x & (CNT_SLOTS - 1)), (unsigned long long)tot);
+}
+
+// Event counters: added to one of CNT_SLOTS spread copies per counter (no single hot
+// address).  One problem: one workgroup sum per counter.  Several problems: one sum per
+// wavefront whose lanes share a problem, single lanes otherwise.
+template <bool BATCHED>
+__device__ __forceinline__ void flush_events(unsigned long long* __restrict__ cnt, const AdvEvents& ev, int prob)
+{
+    const int lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (!BATCHED) {
+        __shared__ int wsum[4][NCOUNT];
+        int v[NCOUNT];
+        wave_events(ev, v);
+        if (lane == 0)
+            for (int q = 0; q < NCOUNT; ++q) wsum[wid][q] = v[q];
+        __syncthreads();
+        if (threadIdx.x < NCOUNT) {
+            const int q = threadIdx.x;
+            int tot = 0;
+            for (int w = 0; w < nw; ++w) tot += wsum[w][q];
+            if (tot) atomicAdd(cnt + q * CNT_SLOTS + (blockIdx.x & (CNT_SLOTS - 1)), (unsigned long long)tot);
+        }
+        return;
     }
+    const unsigned long long act = __ballot(prob >= 0);
+    if (!act) return;
+    const int p0 = __shfl(prob, __ffsll((long long)act) - 1);
+    const int slot = (int)((blockIdx.x * (unsigned)nw + (unsigned)wid) & (CNT_SLOTS - 1));
+    if (!__ballot(prob >= 0 && prob != p0)) {
+        int v[NCOUNT];
+        wave_events(ev, v);
+        if (lane < NCOUNT && v[lane])
+            atomicAdd(cnt + ((int64_t)p0 * NCOUNT + lane) * CNT_SLOTS + slot, (unsigned long long)v[lane]);
+        return;
+    }
+    if (prob < 0) return;
+    const int own[NCOUNT] = {ev.ev_a != 0, ev.ev_b != 0, ev.refl, ev.fb, ev.omrefl != 0, ev.clamp != 0,
+                             ev.steps, ev.src != 0};
+    for (int q = 0; q < NCOUNT; ++q)
+        if (own[q]) atomicAdd(cnt + ((int64_t)prob * NCOUNT + q) * CNT_SLOTS + slot, (unsigned long long)own[q]);
 }
 
 // particles per new host element: runs of equal keys among the lanes share one atomic
-__device__ __forceinline__ void count_new_hosts(const AdvanceArgs& a, int32_t key)
+__device__ __forceinline__ void count_new_hosts(int32_t* __restrict__ counts, int32_t key)
 {
     int leader, len, rank;
     wave_runs(key, leader, len, rank);
-    if (rank == 0 && key >= 0) atomicAdd(a.counts + key, len);
+    if (rank == 0 && key >= 0) atomicAdd(counts + key, len);
 }
 
 // Particle loop: one thread per used slot (merged particles are dead slots, elem < 0)
-__global__ void __launch_bounds__(256) k_advance(AdvanceArgs a)
+template <class R, bool BATCHED>
+__global__ void __launch_bounds__(256) k_advance(AdvanceArgs<R> a)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t nslots = *a.nslots;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nslots = a.meta[0];
+    const uint32_t step = (uint32_t)a.meta[4];
     int32_t key = -1;
+    int prob = -1;
     AdvEvents ev = {0, 0, 0, 0, 0, 0, 0, 0};
     if (i < nslots) {
         int32_t e = a.s.elem[i];
@@ -305,10 +352,10 @@ __global__ void __launch_bounds__(256) k_advance(AdvanceArgs a)
             atomicOr(a.err, ERR_BADELEM);
             e = -1;
         }
-        if (e >= 0) key = advance_one(a, i, e, ev);
+        if (e >= 0) key = advance_one<R, BATCHED>(a, i, e, step, ev, prob);
     }
-    count_new_hosts(a, key);
-    flush_events(a, ev);
+    count_new_hosts(a.counts, key);
+    flush_events<BATCHED>(a.cnt, ev, prob);
 }
 
 // =====================================================================================
@@ -441,7 +488,7 @@ __global__ void __launch_bounds__(256) k_scatter(const int32_t* __restrict__ ele
 // element pass (Sec. 3.5, App. A, Eqs. 24-25; Sec. 3.3)
 // =====================================================================================
 // (velocity component, pid) as a pair of integers whose lexicographic order is the
-// order of the doubles (-0 is first folded onto +0); a strict total order for any bits
+// order of the reals (-0 is first folded onto +0); a strict total order for any bits
 struct SortKey {
     uint64_t k;
     uint64_t p;
@@ -450,6 +497,11 @@ __device__ __forceinline__ uint64_t order_bits(double v)
 {
     const uint64_t u = (uint64_t)__double_as_longlong(v + 0.0);
     return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ uint64_t order_bits(float v)
+{
+    const uint32_t u = (uint32_t)__float_as_uint(v + 0.0f);
+    return (uint64_t)((u >> 31) ? ~u : (u | 0x80000000u));
 }
 __device__ __forceinline__ bool key_less(const SortKey& a, uint64_t bk, uint64_t bp)
 {
@@ -492,12 +544,47 @@ __device__ __forceinline__ int div_small(int a, int b)
 // memory safety against corrupted input
 __device__ __forceinline__ int clampi(int j, int n) { return j < 0 ? 0 : (j >= n ? n - 1 : j); }
 
-template <int NT>
-__device__ __forceinline__ void element_body(const ElementArgs& a, int32_t e, int64_t s0, int n, double* U0,
-                                             double* U1, double* U2, uint64_t* PID, SortKey* kp, int32_t* ordA,
-                                             int32_t* ordB, double* bmean, double* red)
+// IECM mixing fraction of element e, Eq. (24): f = min(dt / t_m, 1); 0 when not mixing
+__device__ __forceinline__ double mix_fraction(int32_t mix, double dt, double tm)
+{
+    double f = mix ? dt / tm : 0.0;
+    return f > 1.0 ? 1.0 : f;
+}
+
+// Per-vertex partial sums of one particle (Sec. 3.3): weight, shifted first moments and
+// shifted products, accumulated with shape-function weight w * lambda_v.
+template <class R>
+__device__ __forceinline__ void add_partials(Acc<R> (&acc)[3][NPART], const R (&rs)[3][5], const R lam[3], R w,
+                                             R u0, R u1, R u2, R om, R psi)
+{
+    const R q5[5] = {u0, u1, u2, om, psi};
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const R wl = w * lam[v];
+        R d[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) d[q] = q5[q] - rs[v][q];
+        acc[v][0].add(wl);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[v][1 + q].add(wl * d[q]);
+        acc[v][6].add(wl * d[0] * d[0]);
+        acc[v][7].add(wl * d[1] * d[1]);
+        acc[v][8].add(wl * d[2] * d[2]);
+        acc[v][9].add(wl * d[0] * d[1]);
+        acc[v][10].add(wl * d[0] * d[2]);
+        acc[v][11].add(wl * d[1] * d[2]);
+        acc[v][12].add(wl * d[4] * d[4]);
+    }
+}
+
+template <int NT, class R>
+__device__ __forceinline__ void element_body(const ElementArgs<R>& a, int32_t e, int64_t s0, int n, R* U0, R* U1,
+                                             R* U2, uint64_t* PID, SortKey* kp, int32_t* ordA, int32_t* ordB,
+                                             R* bmean, R* red)
 {
     const int tid = threadIdx.x;
+    const ElemGeo* G = a.geo + e;
+    const ProbParams& P = a.prm[G->prob];
     // load velocities and pids of the element's particles (load order j)
     for (int j = tid; j < n; j += NT) {
         const int64_t gi = a.idx[s0 + j];
@@ -509,12 +596,12 @@ __device__ __forceinline__ void element_body(const ElementArgs& a, int32_t e, in
     }
     __syncthreads();
     int g0, g1, g2;
-    const int Cp = bin_structure(n, a.bins0, a.bins1, a.bins2, a.minpb, g0, g1, g2);
+    const int Cp = bin_structure(n, P.bins0, P.bins1, P.bins2, P.minpb, g0, g1, g2);
     const int gl[3] = {g0, g1, g2};
     // three levels: sort every group of the previous level by (U_l, pid) (rank sort)
     long long C = 1;
     for (int l = 0; l < 3; ++l) {
-        const double* Ul = l == 0 ? U0 : (l == 1 ? U1 : U2);
+        const R* Ul = l == 0 ? U0 : (l == 1 ? U1 : U2);
         for (int pos = tid; pos < n; pos += NT) {
             const int j = clampi(ordA[pos], n);
             kp[pos].k = order_bits(Ul[j]);
@@ -537,47 +624,41 @@ __device__ __forceinline__ void element_body(const ElementArgs& a, int32_t e, in
         C *= gl[l];
     }
     // bin means of psi, weighted (App. A)
-    double* wacc = reinterpret_cast<double*>(kp);
+    R* wacc = reinterpret_cast<R*>(kp);
     for (int pos = tid; pos < n; pos += NT) {
         const int64_t gi = a.idx[s0 + clampi(ordA[pos], n)];
-        const double w = a.in.w[gi];
+        const R w = a.in.w[gi];
         wacc[2 * pos] = w * a.in.psi[gi];
         wacc[2 * pos + 1] = w;
     }
     __syncthreads();
     for (int b = tid; b < Cp; b += NT) {
         const int lo = (int)(((long long)b * n + Cp - 1) / Cp), hi = (int)(((long long)(b + 1) * n + Cp - 1) / Cp);
-        double sw = 0.0, swp = 0.0;
+        Acc<R> sw, swp;
         for (int q = lo; q < hi; ++q) {
-            swp += wacc[2 * q];
-            sw += wacc[2 * q + 1];
+            swp.add(wacc[2 * q]);
+            sw.add(wacc[2 * q + 1]);
         }
-        bmean[b] = swp / sw;
+        bmean[b] = swp.value() / sw.value();
     }
     __syncthreads();
 
-    // IECM (Eq. 24) with f = min(dt / t_m, 1); statistics partials; canonical write-out
-    double fmix = a.dt / a.tm[e];
-    fmix = fmix > 1.0 ? 1.0 : fmix;
-    const ElemGeo* G = a.geo + e;
+    // IECM (Eq. 24); statistics partials; canonical write-out
+    const R fmix = (R)mix_fraction(a.mix, P.dt, a.tm[e]);
     const double inv_area = 1.0 / G->area;
-    double rs[3][5];
+    R rs[3][5];
 #pragma unroll
     for (int v = 0; v < 3; ++v)
 #pragma unroll
         for (int q = 0; q < 5; ++q) rs[v][q] = a.shift[(int64_t)G->node[v] * 5 + q];
-    double acc[3][NPART];
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-        for (int q = 0; q < NPART; ++q) acc[v][q] = 0.0;
+    Acc<R> acc[3][NPART];
     for (int pos = tid; pos < n; pos += NT) {
         const int j = clampi(ordA[pos], n);
         const int64_t gi = a.idx[s0 + j];
         const double x = a.in.x[gi], y = a.in.y[gi];
-        const double w = a.in.w[gi], om = a.in.om[gi];
-        double psi = a.in.psi[gi];
-        const double u0 = U0[j], u1 = U1[j], u2 = U2[j];
+        const R w = a.in.w[gi], om = a.in.om[gi];
+        R psi = a.in.psi[gi];
+        const R u0 = U0[j], u1 = U1[j], u2 = U2[j];
         const int b = (int)(((long long)Cp * pos) / n);
         psi = psi - fmix * (psi - bmean[b]);
         const int64_t o = s0 + pos;
@@ -593,25 +674,8 @@ __device__ __forceinline__ void element_body(const ElementArgs& a, int32_t e, in
         a.out.elem[o] = e;
         double na, nb, nc;
         area_coords(G, x, y, na, nb, nc);
-        const double lam[3] = {na * inv_area, nb * inv_area, nc * inv_area};
-        const double q5[5] = {u0, u1, u2, om, psi};
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-            const double wl = w * lam[v];
-            double d[5];
-#pragma unroll
-            for (int q = 0; q < 5; ++q) d[q] = q5[q] - rs[v][q];
-            acc[v][0] += wl;
-#pragma unroll
-            for (int q = 0; q < 5; ++q) acc[v][1 + q] += wl * d[q];
-            acc[v][6] += wl * d[0] * d[0];
-            acc[v][7] += wl * d[1] * d[1];
-            acc[v][8] += wl * d[2] * d[2];
-            acc[v][9] += wl * d[0] * d[1];
-            acc[v][10] += wl * d[0] * d[2];
-            acc[v][11] += wl * d[1] * d[2];
-            acc[v][12] += wl * d[4] * d[4];
-        }
+        const R lam[3] = {(R)(na * inv_area), (R)(nb * inv_area), (R)(nc * inv_area)};
+        add_partials<R>(acc, rs, lam, w, u0, u1, u2, om, psi);
     }
     // fixed-order reduction: butterfly inside each wavefront, then waves in order
     const int lane = lane_id(), wid = tid >> 6;
@@ -619,27 +683,35 @@ __device__ __forceinline__ void element_body(const ElementArgs& a, int32_t e, in
     for (int v = 0; v < 3; ++v)
 #pragma unroll
         for (int q = 0; q < NPART; ++q) {
-            const double s = wave_sum_double(acc[v][q]);
+            const R s = wave_sum_real<R>(acc[v][q].value());
             if (lane == 0) red[wid * 3 * NPART + v * NPART + q] = s;
         }
     __syncthreads();
     if (tid < 3 * NPART) {
-        double s = 0.0;
-        for (int w = 0; w < NT / 64; ++w) s += red[w * 3 * NPART + tid];
-        a.part[(int64_t)e * 3 * NPART + tid] = s;
+        Acc<R> s;
+        for (int w = 0; w < NT / 64; ++w) s.add(red[w * 3 * NPART + tid]);
+        a.part[(int64_t)e * 3 * NPART + tid] = s.value();
     }
+}
+
+// on-chip layout of the workgroup kernel: [reduction][bin means][keys][pids][U0 U1 U2][ordA ordB]
+template <class R>
+size_t element_pass_smem(int lds_max)
+{
+    return (size_t)(EP_NT / 64) * 3 * NPART * sizeof(double) + MAXBINS * sizeof(double) +
+           (size_t)lds_max * (sizeof(SortKey) + sizeof(uint64_t) + 3 * sizeof(R) + 2 * sizeof(int32_t));
 }
 
 // Elements with more particles than the wavefront kernel holds: one workgroup per element,
 // taken from the worklist the wavefront kernel fills (on-chip keys up to lds_max
 // particles, global scratch at the element's segment offset above that).
-template <int NT>
-__global__ void __launch_bounds__(NT) k_element_block(ElementArgs a)
+template <int NT, class R>
+__global__ void __launch_bounds__(NT) k_element_block(ElementArgs<R> a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    double* red = reinterpret_cast<double*>(smem);                 // [NT/64][39]
-    double* bmean = red + (NT / 64) * 3 * NPART;                  // [MAXBINS]
-    unsigned char* p = reinterpret_cast<unsigned char*>(bmean + MAXBINS);
+    R* red = reinterpret_cast<R*>(smem);                                   // [NT/64][39]
+    R* bmean = reinterpret_cast<R*>(smem + (NT / 64) * 3 * NPART * sizeof(double));   // [MAXBINS]
+    unsigned char* p = smem + (NT / 64) * 3 * NPART * sizeof(double) + MAXBINS * sizeof(double);
     const int nbig = *a.big_count;
     for (int k = blockIdx.x; k < nbig; k += gridDim.x) {
         const int32_t e = a.big_list[k];
@@ -648,23 +720,23 @@ __global__ void __launch_bounds__(NT) k_element_block(ElementArgs a)
         if (n <= a.lds_max) {
             const int M = a.lds_max;
             SortKey* kp = reinterpret_cast<SortKey*>(p);
-            double* U0 = reinterpret_cast<double*>(kp + M);
-            double* U1 = U0 + M;
-            double* U2 = U1 + M;
-            uint64_t* PID = reinterpret_cast<uint64_t*>(U2 + M);
-            int32_t* ordA = reinterpret_cast<int32_t*>(PID + M);
+            uint64_t* PID = reinterpret_cast<uint64_t*>(kp + M);
+            R* U0 = reinterpret_cast<R*>(PID + M);
+            R* U1 = U0 + M;
+            R* U2 = U1 + M;
+            int32_t* ordA = reinterpret_cast<int32_t*>(U2 + M);
             int32_t* ordB = ordA + M;
-            element_body<NT>(a, e, s0, n, U0, U1, U2, PID, kp, ordA, ordB, bmean, red);
+            element_body<NT, R>(a, e, s0, n, U0, U1, U2, PID, kp, ordA, ordB, bmean, red);
         } else {
             const int64_t cap = a.cap;
             SortKey* kp = reinterpret_cast<SortKey*>(a.gkey) + s0;
-            double* U0 = a.gu3 + s0;
-            double* U1 = a.gu3 + cap + s0;
-            double* U2 = a.gu3 + 2 * cap + s0;
+            R* U0 = reinterpret_cast<R*>(a.gu3) + s0;
+            R* U1 = reinterpret_cast<R*>(a.gu3) + cap + s0;
+            R* U2 = reinterpret_cast<R*>(a.gu3) + 2 * cap + s0;
             uint64_t* PID = reinterpret_cast<uint64_t*>(a.gu3 + 3 * cap) + s0;
             int32_t* ordA = a.gord + s0;
             int32_t* ordB = a.gord + cap + s0;
-            element_body<NT>(a, e, s0, n, U0, U1, U2, PID, kp, ordA, ordB, bmean, red);
+            element_body<NT, R>(a, e, s0, n, U0, U1, U2, PID, kp, ordA, ordB, bmean, red);
         }
         __syncthreads();
     }
@@ -688,8 +760,8 @@ struct WaveBlock {
 // in load order while the three sort levels rank (U_l, pid) keys staged in LDS; then each
 // lane takes the particles at canonical positions lane + 64 r, so bin sums, partial sums
 // and the coalesced write-out follow the canonical order only.
-template <int PPL>
-__global__ void __launch_bounds__(256) k_element_wave(ElementArgs a)
+template <int PPL, class R>
+__global__ void __launch_bounds__(256) k_element_wave(ElementArgs<R> a)
 {
     constexpr int N = 64 * PPL;
     constexpr int RED = (13 * 65 * 8 + 15) & ~15;         // transposed reduction, padded rows
@@ -706,14 +778,14 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs a)
     uint64_t* kk = reinterpret_cast<uint64_t*>(base);          // [N] keys by position
     uint64_t* kpid = kk + N;                                     // [N] pids by position
     uint64_t* claim = kpid + N;                                  // [N] rank collision check
-    double* wacc = reinterpret_cast<double*>(base);
-    double* red = reinterpret_cast<double*>(base);
+    R* wacc = reinterpret_cast<R*>(base);
+    R* red = reinterpret_cast<R*>(base);
     int32_t* ord = reinterpret_cast<int32_t*>(base + R1);
-    double* bmean = reinterpret_cast<double*>(base + R1 + 4 * N);
+    R* bmean = reinterpret_cast<R*>(base + R1 + 4 * N);
     const int64_t s0 = __builtin_amdgcn_readfirstlane(a.start[e]);
     const int n = __builtin_amdgcn_readfirstlane(a.start[e + 1]) - (int)s0;
     if (n == 0) {
-        if (lane < 3 * NPART) a.part[e * 3 * NPART + lane] = 0.0;
+        if (lane < 3 * NPART) a.part[e * 3 * NPART + lane] = R(0);
         return;
     }
     if (n > N) {
@@ -723,16 +795,18 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs a)
         }
         return;
     }
+    const ElemGeo* G = a.geo + e;
+    const ProbParams& P = a.prm[G->prob];
     // load order: particle j = lane + 64 r
     int gi[PPL], pos[PPL];
-    double U0[PPL], U1[PPL], U2[PPL];
+    R U0[PPL], U1[PPL], U2[PPL];
     uint64_t pd[PPL];
 #pragma unroll
     for (int r = 0; r < PPL; ++r) {
         const int j = lane + 64 * r;
         pos[r] = j;
         gi[r] = 0;
-        U0[r] = U1[r] = U2[r] = 0.0;
+        U0[r] = U1[r] = U2[r] = R(0);
         pd[r] = 0;
         if (j < n) {
             gi[r] = a.idx[s0 + j];
@@ -743,7 +817,7 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs a)
         }
     }
     int g0, g1, g2;
-    const int Cp = bin_structure(n, a.bins0, a.bins1, a.bins2, a.minpb, g0, g1, g2);
+    const int Cp = bin_structure(n, P.bins0, P.bins1, P.bins2, P.minpb, g0, g1, g2);
     const int gl[3] = {g0, g1, g2};
     long long C = 1;
 #pragma unroll
@@ -828,12 +902,12 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs a)
         if (lane + 64 * r < n) ord[pos[r]] = gi[r];
     wave_sync();
     int gp[PPL];
-    double ws[PPL], ps[PPL];
+    R ws[PPL], ps[PPL];
 #pragma unroll
     for (int r = 0; r < PPL; ++r) {
         const int p = lane + 64 * r;
         gp[r] = 0;
-        ws[r] = ps[r] = 0.0;
+        ws[r] = ps[r] = R(0);
         if (p < n) {
             gp[r] = ord[p];
             ws[r] = a.in.w[gp[r]];
@@ -845,40 +919,35 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs a)
     wave_sync();
     for (int b = lane; b < Cp; b += 64) {
         const int lo = div_small(b * n + Cp - 1, Cp), hi = div_small((b + 1) * n + Cp - 1, Cp);
-        double sw = 0.0, swp = 0.0;
+        Acc<R> sw, swp;
         for (int q = lo; q < hi; ++q) {
-            swp += wacc[2 * q];
-            sw += wacc[2 * q + 1];
+            swp.add(wacc[2 * q]);
+            sw.add(wacc[2 * q + 1]);
         }
-        bmean[b] = swp / sw;
+        bmean[b] = swp.value() / sw.value();
     }
     wave_sync();
 
-    double fmix = a.dt / a.tm[e];
-    fmix = fmix > 1.0 ? 1.0 : fmix;
-    const ElemGeo* G = a.geo + e;
+    const R fmix = (R)mix_fraction(a.mix, P.dt, a.tm[e]);
     const double inv_area = 1.0 / G->area;
-    double rs[3][5];
+    R rs[3][5];
 #pragma unroll
     for (int v = 0; v < 3; ++v)
 #pragma unroll
         for (int q = 0; q < 5; ++q) rs[v][q] = a.shift[(int64_t)G->node[v] * 5 + q];
-    double acc[3][NPART];
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-        for (int q = 0; q < NPART; ++q) acc[v][q] = 0.0;
+    Acc<R> acc[3][NPART];
 #pragma unroll
     for (int r = 0; r < PPL; ++r) {
         const int p = lane + 64 * r;
         if (p >= n) continue;
         const int64_t g = gp[r];
-        const double x = a.in.x[g], y = a.in.y[g], om = a.in.om[g];
-        const double u0 = a.in.u0[g], u1 = a.in.u1[g], u2 = a.in.u2[g];
+        const double x = a.in.x[g], y = a.in.y[g];
+        const R om = a.in.om[g];
+        const R u0 = a.in.u0[g], u1 = a.in.u1[g], u2 = a.in.u2[g];
         const uint64_t pid = a.in.pid[g];
         const int b = div_small(Cp * p, n);
-        const double psi = ps[r] - fmix * (ps[r] - bmean[b]);
-        const double w = ws[r];
+        const R psi = ps[r] - fmix * (ps[r] - bmean[b]);
+        const R w = ws[r];
         const int64_t o = s0 + p;
         a.out.x[o] = x;
         a.out.y[o] = y;
@@ -892,105 +961,95 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs a)
         a.out.elem[o] = (int32_t)e;
         double na, nb, nc;
         area_coords(G, x, y, na, nb, nc);
-        const double lam[3] = {na * inv_area, nb * inv_area, nc * inv_area};
-        const double q5[5] = {u0, u1, u2, om, psi};
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-            const double wl = w * lam[v];
-            double d[5];
-#pragma unroll
-            for (int q = 0; q < 5; ++q) d[q] = q5[q] - rs[v][q];
-            acc[v][0] += wl;
-#pragma unroll
-            for (int q = 0; q < 5; ++q) acc[v][1 + q] += wl * d[q];
-            acc[v][6] += wl * d[0] * d[0];
-            acc[v][7] += wl * d[1] * d[1];
-            acc[v][8] += wl * d[2] * d[2];
-            acc[v][9] += wl * d[0] * d[1];
-            acc[v][10] += wl * d[0] * d[2];
-            acc[v][11] += wl * d[1] * d[2];
-            acc[v][12] += wl * d[4] * d[4];
-        }
+        const R lam[3] = {(R)(na * inv_area), (R)(nb * inv_area), (R)(nc * inv_area)};
+        add_partials<R>(acc, rs, lam, w, u0, u1, u2, om, psi);
     }
     // fixed-order wavefront reduction through LDS: row q holds the 64 lanes' values
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
 #pragma unroll
-        for (int q = 0; q < NPART; ++q) red[q * 65 + lane] = acc[v][q];
+        for (int q = 0; q < NPART; ++q) red[q * 65 + lane] = acc[v][q].value();
         wave_sync();
         if (lane < NPART) {
-            double s = 0.0;
-            for (int l = 0; l < 64; ++l) s += red[lane * 65 + l];
-            a.part[e * 3 * NPART + v * NPART + lane] = s;
+            Acc<R> s;
+            for (int l = 0; l < 64; ++l) s.add(red[lane * 65 + l]);
+            a.part[e * 3 * NPART + v * NPART + lane] = s.value();
         }
         wave_sync();
     }
 }
 
-size_t element_pass_smem(int lds_max)
-{
-    return (size_t)(EP_NT / 64) * 3 * NPART * sizeof(double) + MAXBINS * sizeof(double) +
-           (size_t)lds_max * (sizeof(SortKey) + 4 * sizeof(double) + 2 * sizeof(int32_t));
-}
-
 // =====================================================================================
 // node finalize (Sec. 3.3): fixed-order sum over the elements around the node
 // =====================================================================================
-__global__ void __launch_bounds__(256) k_node_finalize(NodeArgs a)
+template <class R>
+__global__ void __launch_bounds__(256) k_node_finalize(NodeArgs<R> a)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i == 0) {
         a.meta[0] = a.start[a.ne];   // used slots after compaction
         a.meta[1] = a.start[a.ne];   // live particles
+        if (a.advance_step) a.meta[4] += 1;   // step counter of the random streams
         *a.big_count = 0;            // worklist of large elements, empty for the next pass
     }
     if (i >= a.nn) return;
-    double S[NPART];
-#pragma unroll
-    for (int q = 0; q < NPART; ++q) S[q] = 0.0;
+    Acc<R> S[NPART];
     for (int64_t j = a.n2e_ptr[i]; j < a.n2e_ptr[i + 1]; ++j) {
-        const double* pp = a.part + (int64_t)a.n2e[j] * NPART;
+        const R* pp = a.part + (int64_t)a.n2e[j] * NPART;
 #pragma unroll
-        for (int q = 0; q < NPART; ++q) S[q] += pp[q];
+        for (int q = 0; q < NPART; ++q) S[q].add(pp[q]);
     }
+    // the division by the nodal weight and the moments are FP64 in both forms
     double* o = a.stats + i * NSTAT;
-    double* r = a.shift + i * 5;
-    const double W = S[0];
+    R* r = a.shift + i * 5;
+    const double W = (double)S[0].value();
     o[0] = W;
     if (W == 0.0) {
         const double nan = __builtin_nan("");
         for (int q = 1; q < NSTAT; ++q) o[q] = nan;
-        for (int q = 0; q < 5; ++q) r[q] = 0.0;
+        for (int q = 0; q < 5; ++q) r[q] = R(0);
         return;
     }
     double d[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) d[q] = S[1 + q] / W;
+    for (int q = 0; q < 5; ++q) d[q] = (double)S[1 + q].value() / W;
 #pragma unroll
-    for (int q = 0; q < 5; ++q) o[1 + q] = r[q] + d[q];
-    o[6] = S[6] / W - d[0] * d[0];
-    o[7] = S[7] / W - d[1] * d[1];
-    o[8] = S[8] / W - d[2] * d[2];
-    o[9] = S[9] / W - d[0] * d[1];
-    o[10] = S[10] / W - d[0] * d[2];
-    o[11] = S[11] / W - d[1] * d[2];
-    o[12] = S[12] / W - d[4] * d[4];
+    for (int q = 0; q < 5; ++q) o[1 + q] = (double)r[q] + d[q];
+    o[6] = (double)S[6].value() / W - d[0] * d[0];
+    o[7] = (double)S[7].value() / W - d[1] * d[1];
+    o[8] = (double)S[8].value() / W - d[2] * d[2];
+    o[9] = (double)S[9].value() / W - d[0] * d[1];
+    o[10] = (double)S[10].value() / W - d[0] * d[2];
+    o[11] = (double)S[11].value() / W - d[1] * d[2];
+    o[12] = (double)S[12].value() / W - d[4] * d[4];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) r[q] = o[1 + q];
+    for (int q = 0; q < 5; ++q) r[q] = (R)o[1 + q];
 }
 
 // =====================================================================================
-// set-up (Sec. 3.7): ppe particles per element
+// set-up (Sec. 3.7): ppe particles per element of every problem
 // =====================================================================================
-__global__ void __launch_bounds__(256) k_init(InitArgs a)
+template <class R>
+__global__ void __launch_bounds__(256) k_init(InitArgs<R> a)
 {
+    using M = RMath<R>;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
-    const int32_t e = (int32_t)(i / a.ppe);
+    // problem of slot i: the last one whose first slot is <= i
+    int lo = 0, hi = a.n_problems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.prm[mid].soff <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    const ProbParams& P = a.prm[lo];
+    const int64_t k = i - P.soff;
+    const int32_t e = (int32_t)(P.eoff + k / P.ppe);
     const ElemGeo* G = a.geo + e;
-    const uint64_t pid = (uint64_t)i;
-    const Words4 wA = rng_draw(a.key, pid, 0, TAG_INIT, 0);
-    const Words4 wB = rng_draw(a.key, pid, 0, TAG_INIT, 1);
+    const uint64_t pid = (uint64_t)k;
+    const Words4 wA = rng_draw(P.key, pid, 0, TAG_INIT, 0);
+    const Words4 wB = rng_draw(P.key, pid, 0, TAG_INIT, 1);
+    // uniform point in the element (positions are FP64 in both forms)
     double s = u01(wA.w0), t = u01(wA.w1);
     if (s + t > 1.0) {
         s = 1.0 - s;
@@ -1000,42 +1059,45 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a)
     const double y = G->y[0] + s * (G->y[1] - G->y[0]) + t * (G->y[2] - G->y[0]);
     double na, nb, nc;
     area_coords(G, x, y, na, nb, nc);
-    const double la = na / G->area, lb = nb / G->area, lc = nc / G->area;
-    const double* FA = a.node + (int64_t)G->node[0] * NODE_STRIDE;
-    const double* FB = a.node + (int64_t)G->node[1] * NODE_STRIDE;
-    const double* FC = a.node + (int64_t)G->node[2] * NODE_STRIDE;
-    double z0, z1, z2, z3;
-    box_muller(wA.w2, wA.w3, z0, z1);
-    box_muller(wB.w0, wB.w1, z2, z3);
-    const double mu0 = la * FA[NF_MU] + lb * FB[NF_MU] + lc * FC[NF_MU];
-    const double mu1 = la * FA[NF_MU + 1] + lb * FB[NF_MU + 1] + lc * FC[NF_MU + 1];
-    const double mu2 = la * FA[NF_MU + 2] + lb * FB[NF_MU + 2] + lc * FC[NF_MU + 2];
-    const double omm = la * FA[NF_OM] + lb * FB[NF_OM] + lc * FC[NF_OM];
+    const R la = (R)(na / G->area), lb = (R)(nb / G->area), lc = (R)(nc / G->area);
+    const R* FA = a.node + (int64_t)G->node[0] * NODE_STRIDE;
+    const R* FB = a.node + (int64_t)G->node[1] * NODE_STRIDE;
+    const R* FC = a.node + (int64_t)G->node[2] * NODE_STRIDE;
+    R z0, z1, z2, z3;
+    M::normal2(wA.w2, wA.w3, z0, z1);
+    M::normal2(wB.w0, wB.w1, z2, z3);
+    const R mu0 = la * FA[NF_MU] + lb * FB[NF_MU] + lc * FC[NF_MU];
+    const R mu1 = la * FA[NF_MU + 1] + lb * FB[NF_MU + 1] + lc * FC[NF_MU + 1];
+    const R mu2 = la * FA[NF_MU + 2] + lb * FB[NF_MU + 2] + lc * FC[NF_MU + 2];
+    const R omm = la * FA[NF_OM] + lb * FB[NF_OM] + lc * FC[NF_OM];
+    const R sig = (R)P.u_sigma;
     a.s.x[i] = x;
     a.s.y[i] = y;
-    a.s.u0[i] = mu0 + a.u_sigma * z0;
-    a.s.u1[i] = mu1 + a.u_sigma * z1;
-    a.s.u2[i] = mu2 + a.u_sigma * z2;
-    a.s.om[i] = gamma_draw(a.omega_shape, omm, a.key, pid, 0, TAG_INIT_GAMMA);
-    double dx = x - a.src_x, dy = y - a.src_y;
-    if (a.period > 0.0) {
-        if (dx > 0.5 * a.period) dx -= a.period;
-        else if (dx < -0.5 * a.period) dx += a.period;
+    a.s.u0[i] = mu0 + sig * z0;
+    a.s.u1[i] = mu1 + sig * z1;
+    a.s.u2[i] = mu2 + sig * z2;
+    a.s.om[i] = gamma_draw<R>((R)P.omega_shape, omm, P.key, pid, 0, TAG_INIT_GAMMA);
+    double dx = x - P.src_x, dy = y - P.src_y;
+    if (P.period > 0.0) {
+        if (dx > 0.5 * P.period) dx -= P.period;
+        else if (dx < -0.5 * P.period) dx += P.period;
     }
-    a.s.psi[i] = (dx * dx + dy * dy < a.src_r2) ? 1.0 : 0.0;
-    a.s.w[i] = 1.0;
+    a.s.psi[i] = (dx * dx + dy * dy < P.src_r2) ? R(1) : R(0);
+    a.s.w[i] = R(1);
     a.s.pid[i] = pid;
     a.s.elem[i] = e;
 }
 
-// micromixing timescale per element, Eq. (25) at the centroid
+// micromixing timescale per element, Eq. (25) at the centroid (FP64 in both forms)
 __global__ void __launch_bounds__(256) k_tm(const ElemGeo* __restrict__ geo, const double* __restrict__ node,
-                                            int64_t ne, ModelC m, double src_x, double src_y, double src_r,
-                                            double period, double* __restrict__ tm)
+                                            int64_t ne, const ProbParams* __restrict__ prm, double* __restrict__ tm)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= ne) return;
     const ElemGeo* G = geo + e;
+    const ProbParams& P = prm[G->prob];
+    const ModelC& m = P.m;
+    const double src_r = sqrt(P.src_r2);
     const double* A = node + (int64_t)G->node[0] * NODE_STRIDE;
     const double* B = node + (int64_t)G->node[1] * NODE_STRIDE;
     const double* C = node + (int64_t)G->node[2] * NODE_STRIDE;
@@ -1046,10 +1108,10 @@ __global__ void __launch_bounds__(256) k_tm(const ElemGeo* __restrict__ geo, con
     const double m0 = cen(NF_MU), m1 = cen(NF_MU + 1), m2 = cen(NF_MU + 2);
     const double Uc = sqrt(m0 * m0 + m1 * m1 + m2 * m2);
     const double cx = (G->x[0] + G->x[1] + G->x[2]) / 3.0, cy = (G->y[0] + G->y[1] + G->y[2]) / 3.0;
-    double dx = cx - src_x, dy = cy - src_y;
-    if (period > 0.0) {
-        if (dx > 0.5 * period) dx -= period;
-        else if (dx < -0.5 * period) dx += period;
+    double dx = cx - P.src_x, dy = cy - P.src_y;
+    if (P.period > 0.0) {
+        if (dx > 0.5 * P.period) dx -= P.period;
+        else if (dx < -0.5 * P.period) dx += P.period;
     }
     const double dist = sqrt(dx * dx + dy * dy);
     const double first = Uc > 0.0 ? m.Cs * cbrt(src_r * src_r / eps) + m.Ct * dist / Uc : __builtin_inf();
@@ -1060,7 +1122,8 @@ __global__ void __launch_bounds__(256) k_tm(const ElemGeo* __restrict__ geo, con
 // =====================================================================================
 // number control (Sec. 3.7, App. B)
 // =====================================================================================
-__global__ void __launch_bounds__(256) k_ctl_plan(ControlArgs a)
+template <class R>
+__global__ void __launch_bounds__(256) k_ctl_plan(ControlArgs<R> a)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     int merged = 0, empty = 0, below = 0, above = 0;
@@ -1075,8 +1138,9 @@ __global__ void __launch_bounds__(256) k_ctl_plan(ControlArgs a)
             c = (a.n_min - n) < n ? (a.n_min - n) : n;
         } else if (n > a.n_max) {
             above = 1;
+            const ProbParams& P = a.prm[a.geo[e].prob];
             int g0, g1, g2;
-            const int Cp = bin_structure(n, a.bins0, a.bins1, a.bins2, a.minpb, g0, g1, g2);
+            const int Cp = bin_structure(n, P.bins0, P.bins1, P.bins2, P.minpb, g0, g1, g2);
             const int want = n - a.n_max;
             for (int j = 0; merged < want; ++j) {
                 bool any = false;
@@ -1086,8 +1150,8 @@ __global__ void __launch_bounds__(256) k_ctl_plan(ControlArgs a)
                     if (size < 2LL * j + 2) continue;
                     any = true;
                     const int64_t r = s0 + first + 2 * j, v = r + 1;
-                    const double wr = a.s.w[r], wv = a.s.w[v];
-                    const double W = wr + wv;
+                    const R wr = a.s.w[r], wv = a.s.w[v];
+                    const R W = wr + wv;
                     a.s.u0[r] = (wr * a.s.u0[r] + wv * a.s.u0[v]) / W;
                     a.s.u1[r] = (wr * a.s.u1[r] + wv * a.s.u1[v]) / W;
                     a.s.u2[r] = (wr * a.s.u2[r] + wv * a.s.u2[v]) / W;
@@ -1112,15 +1176,20 @@ __global__ void __launch_bounds__(256) k_ctl_plan(ControlArgs a)
     }
 }
 
-__global__ void __launch_bounds__(256) k_ctl_apply(ControlArgs a)
+// splits: clones appended after the used slots; new pids continue the problem's numbering
+// in element order
+template <class R>
+__global__ void __launch_bounds__(256) k_ctl_apply(ControlArgs<R> a)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= a.ne) return;
     const int c = a.clone[e];
     if (c == 0) return;
+    const ProbParams& P = a.prm[a.geo[e].prob];
     const int64_t s0 = a.start[e];
     const int64_t n = a.start[e + 1] - a.start[e];
     const int64_t base = *a.nslots + a.off[e];
+    const uint64_t pid0 = P.next_pid + (uint64_t)(a.off[e] - a.off[P.eoff]);
     for (int i = 0; i < c; ++i) {
         const int64_t src = s0 + ((2LL * i + 1) * n) / (2LL * c);
         const int64_t dst = base + i;
@@ -1128,7 +1197,7 @@ __global__ void __launch_bounds__(256) k_ctl_apply(ControlArgs a)
             atomicOr(a.err, ERR_CAPACITY);
             continue;
         }
-        const double w = 0.5 * a.s.w[src];
+        const R w = R(0.5) * a.s.w[src];
         a.s.w[src] = w;
         a.s.x[dst] = a.s.x[src];
         a.s.y[dst] = a.s.y[src];
@@ -1138,14 +1207,15 @@ __global__ void __launch_bounds__(256) k_ctl_apply(ControlArgs a)
         a.s.om[dst] = a.s.om[src];
         a.s.psi[dst] = a.s.psi[src];
         a.s.w[dst] = w;
-        a.s.pid[dst] = a.next_pid + (uint64_t)(a.off[e] + i);
+        a.s.pid[dst] = pid0 + (uint64_t)i;
         a.s.elem[dst] = (int32_t)e;
     }
 }
 
-// slots and live count after control; the device report gets the clone total
+// slots and live count after control, the clone total, and every problem's next pid
 __global__ void k_ctl_finish(int64_t* __restrict__ meta, const int32_t* __restrict__ off, int64_t ne,
-                             const unsigned long long* __restrict__ rep, int64_t cap)
+                             const unsigned long long* __restrict__ rep, int64_t cap, ProbParams* __restrict__ prm,
+                             int32_t n_problems)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const int64_t total = off[ne];
@@ -1153,6 +1223,8 @@ __global__ void k_ctl_finish(int64_t* __restrict__ meta, const int32_t* __restri
     meta[0] = slots > cap ? cap : slots;
     meta[1] = meta[1] - (int64_t)rep[0] + total;
     meta[2] = total;
+    for (int p = 0; p < n_problems; ++p)
+        prm[p].next_pid += (uint64_t)(off[prm[p].eoff + prm[p].ne] - off[prm[p].eoff]);
 }
 
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v)
@@ -1168,24 +1240,45 @@ __global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* __restrict
     if (i < n) p[i] = v;
 }
 
-__global__ void __launch_bounds__(256) k_fill_f64(double* __restrict__ p, int64_t n, double v)
+__global__ void __launch_bounds__(256) k_f64_to_f32(const double* __restrict__ in, float* __restrict__ out, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) p[i] = v;
+    if (i < n) out[i] = (float)in[i];
+}
+
+__global__ void __launch_bounds__(256) k_f32_to_f64(const float* __restrict__ in, double* __restrict__ out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = (double)in[i];
+}
+
+// live particles whose element lies in [lo, hi) (the particles of one problem)
+__global__ void __launch_bounds__(256) k_count_range(const int32_t* __restrict__ elem,
+                                                     const int64_t* __restrict__ nslots, int32_t lo, int32_t hi,
+                                                     unsigned long long* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int in = 0;
+    if (i < *nslots) {
+        const int32_t e = elem[i];
+        in = (e >= lo && e < hi) ? 1 : 0;
+    }
+    const int c = __popcll(__ballot(in != 0));
+    if (lane_id() == 0 && c) atomicAdd(out, (unsigned long long)c);
 }
 
 // initial shift of the single-pass moments: the frozen <U>, <omega> and psi = 0
-__global__ void __launch_bounds__(256) k_shift_init(const double* __restrict__ node, int64_t nn,
-                                                    double* __restrict__ shift)
+template <class R>
+__global__ void __launch_bounds__(256) k_shift_init(const R* __restrict__ node, int64_t nn, R* __restrict__ shift)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= nn) return;
-    const double* F = node + i * NODE_STRIDE;
+    const R* F = node + i * NODE_STRIDE;
     shift[i * 5 + 0] = F[NF_MU];
     shift[i * 5 + 1] = F[NF_MU + 1];
     shift[i * 5 + 2] = F[NF_MU + 2];
     shift[i * 5 + 3] = F[NF_OM];
-    shift[i * 5 + 4] = 0.0;
+    shift[i * 5 + 4] = R(0);
 }
 
 // =====================================================================================
@@ -1193,14 +1286,26 @@ __global__ void __launch_bounds__(256) k_shift_init(const double* __restrict__ n
 // =====================================================================================
 static inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) / nt); }
 
-void launch_advance(const AdvanceArgs& a, int64_t n_ub, hipStream_t s)
+template <class R>
+void launch_advance(const AdvanceArgs<R>& a, int64_t n_ub, bool batched, int block, hipStream_t s)
 {
-    if (n_ub > 0) hipLaunchKernelGGL(k_advance, dim3(blocks_for(n_ub, 256)), dim3(256), 0, s, a);
+    if (n_ub <= 0) return;
+    if (block != 64 && block != 128) block = 256;
+    if (batched)
+        hipLaunchKernelGGL((k_advance<R, true>), dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_advance<R, false>), dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
 }
 void launch_count(const int32_t* elem, const int64_t* nslots, int64_t n_ub, int64_t ne, int32_t* counts,
                   uint32_t* err, hipStream_t s)
 {
     if (n_ub > 0) hipLaunchKernelGGL(k_count, dim3(blocks_for(n_ub, 256)), dim3(256), 0, s, elem, nslots, ne, counts, err);
+}
+void launch_count_range(const int32_t* elem, const int64_t* nslots, int64_t n_ub, int32_t lo, int32_t hi,
+                        unsigned long long* out, hipStream_t s)
+{
+    if (n_ub > 0)
+        hipLaunchKernelGGL(k_count_range, dim3(blocks_for(n_ub, 256)), dim3(256), 0, s, elem, nslots, lo, hi, out);
 }
 int64_t scan_blocks(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE; }
 void launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* tmp, hipStream_t s)
@@ -1217,50 +1322,57 @@ void launch_scatter(const int32_t* elem, const int64_t* nslots, int64_t n_ub, in
     if (n_ub > 0)
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n_ub, 256)), dim3(256), 0, s, elem, nslots, ne, counts, start, idx, err);
 }
+template <class R>
 hipError_t prepare_element_pass(int lds_max)
 {
-    return hipFuncSetAttribute((const void*)k_element_block<EP_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)element_pass_smem(lds_max));
+    return hipFuncSetAttribute((const void*)k_element_block<EP_NT, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)element_pass_smem<R>(lds_max));
 }
-void launch_element_pass(const ElementArgs& a, hipStream_t s)
+template <class R>
+void launch_element_pass(const ElementArgs<R>& a, hipStream_t s)
 {
     const dim3 g4((unsigned)((a.ne + 3) / 4)), b4(256), g2((unsigned)((a.ne + 1) / 2)), b2(128);
     switch (a.ppl) {
-    case 1: hipLaunchKernelGGL(k_element_wave<1>, g4, b4, 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_element_wave<2>, g4, b4, 0, s, a); break;
-    case 3: hipLaunchKernelGGL(k_element_wave<3>, g4, b4, 0, s, a); break;
-    case 4: hipLaunchKernelGGL(k_element_wave<4>, g4, b4, 0, s, a); break;
-    case 5: hipLaunchKernelGGL(k_element_wave<5>, g4, b4, 0, s, a); break;
-    case 6: hipLaunchKernelGGL(k_element_wave<6>, g2, b2, 0, s, a); break;
-    default: hipLaunchKernelGGL(k_element_wave<8>, g2, b2, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_element_wave<1, R>), g4, b4, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_element_wave<2, R>), g4, b4, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_element_wave<3, R>), g4, b4, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_element_wave<4, R>), g4, b4, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_element_wave<5, R>), g4, b4, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_element_wave<6, R>), g2, b2, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_element_wave<8, R>), g2, b2, 0, s, a); break;
     }
-    hipLaunchKernelGGL(k_element_block<EP_NT>, dim3(EP_BIG_BLOCKS), dim3(EP_NT), element_pass_smem(a.lds_max), s, a);
+    hipLaunchKernelGGL((k_element_block<EP_NT, R>), dim3(EP_BIG_BLOCKS), dim3(EP_NT), element_pass_smem<R>(a.lds_max),
+                       s, a);
 }
-void launch_node_finalize(const NodeArgs& a, hipStream_t s)
+template <class R>
+void launch_node_finalize(const NodeArgs<R>& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_node_finalize, dim3(blocks_for(a.nn > 0 ? a.nn : 1, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_node_finalize<R>, dim3(blocks_for(a.nn > 0 ? a.nn : 1, 256)), dim3(256), 0, s, a);
 }
-void launch_init(const InitArgs& a, hipStream_t s)
+template <class R>
+void launch_init(const InitArgs<R>& a, hipStream_t s)
 {
-    if (a.n > 0) hipLaunchKernelGGL(k_init, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, a);
+    if (a.n > 0) hipLaunchKernelGGL(k_init<R>, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, a);
 }
-void launch_tm(const ElemGeo* geo, const double* node, int64_t ne, ModelC m, double sx, double sy, double sr,
-               double period, double* tm, hipStream_t s)
+void launch_tm(const ElemGeo* geo, const double* node, int64_t ne, const ProbParams* prm, double* tm,
+               hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tm, dim3(blocks_for(ne, 256)), dim3(256), 0, s, geo, node, ne, m, sx, sy, sr, period, tm);
+    if (ne > 0) hipLaunchKernelGGL(k_tm, dim3(blocks_for(ne, 256)), dim3(256), 0, s, geo, node, ne, prm, tm);
 }
-void launch_ctl_plan(const ControlArgs& a, hipStream_t s)
+template <class R>
+void launch_ctl_plan(const ControlArgs<R>& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ctl_plan, dim3(blocks_for(a.ne, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_ctl_plan<R>, dim3(blocks_for(a.ne, 256)), dim3(256), 0, s, a);
 }
-void launch_ctl_apply(const ControlArgs& a, hipStream_t s)
+template <class R>
+void launch_ctl_apply(const ControlArgs<R>& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ctl_apply, dim3(blocks_for(a.ne, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_ctl_apply<R>, dim3(blocks_for(a.ne, 256)), dim3(256), 0, s, a);
 }
 void launch_ctl_finish(int64_t* meta, const int32_t* off, int64_t ne, const unsigned long long* rep, int64_t cap,
-                       hipStream_t s)
+                       ProbParams* prm, int32_t n_problems, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ctl_finish, dim3(1), dim3(64), 0, s, meta, off, ne, rep, cap);
+    hipLaunchKernelGGL(k_ctl_finish, dim3(1), dim3(64), 0, s, meta, off, ne, rep, cap, prm, n_problems);
 }
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s)
 {
@@ -1270,13 +1382,33 @@ void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hip
 {
     if (n > 0) hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
 }
-void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s)
+void launch_f64_to_f32(const double* in, float* out, int64_t n, hipStream_t s)
 {
-    if (n > 0) hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+    if (n > 0) hipLaunchKernelGGL(k_f64_to_f32, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
 }
-void launch_shift_init(const double* node, int64_t nn, double* shift, hipStream_t s)
+void launch_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_shift_init, dim3(blocks_for(nn, 256)), dim3(256), 0, s, node, nn, shift);
+    if (n > 0) hipLaunchKernelGGL(k_f32_to_f64, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
 }
+template <class R>
+void launch_shift_init(const R* node, int64_t nn, R* shift, hipStream_t s)
+{
+    if (nn > 0) hipLaunchKernelGGL(k_shift_init<R>, dim3(blocks_for(nn, 256)), dim3(256), 0, s, node, nn, shift);
+}
+
+// both forms of the state
+#define PDF_INSTANTIATE(R)                                                                               \
+    template void launch_advance<R>(const AdvanceArgs<R>&, int64_t, bool, int, hipStream_t);             \
+    template hipError_t prepare_element_pass<R>(int);                                                    \
+    template size_t element_pass_smem<R>(int);                                                           \
+    template void launch_element_pass<R>(const ElementArgs<R>&, hipStream_t);                            \
+    template void launch_node_finalize<R>(const NodeArgs<R>&, hipStream_t);                              \
+    template void launch_init<R>(const InitArgs<R>&, hipStream_t);                                       \
+    template void launch_ctl_plan<R>(const ControlArgs<R>&, hipStream_t);                                \
+    template void launch_ctl_apply<R>(const ControlArgs<R>&, hipStream_t);                               \
+    template void launch_shift_init<R>(const R*, int64_t, R*, hipStream_t);
+PDF_INSTANTIATE(double)
+PDF_INSTANTIATE(float)
+#undef PDF_INSTANTIATE
 
 }  // namespace pdfgpu

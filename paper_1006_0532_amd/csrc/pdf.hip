@@ -62,11 +62,11 @@ struct Timed {
     hipEvent_t a = nullptr;
     Timed(pdf_ens_s* e, int i, hipStream_t st) : E(e), id(i), s(st)
     {
-        if (E->timing && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+        if (E->timing && !E->capturing && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
     }
     ~Timed()
     {
-        if (!E->timing || !a) return;
+        if (!a) return;
         hipEvent_t b = nullptr;
         if (hipEventCreate(&b) == hipSuccess) {
             (void)hipEventRecord(b, s);
@@ -106,42 +106,41 @@ pdf_status check_device_error(pdf_ens_s* E)
     return PDF_E_STATE;
 }
 
-Soa& cur(pdf_ens_s* E) { return E->buf[E->cur]; }
 
-// group the particles of the current buffer by element, bin them, mix (dt > 0), write
+SoaRaw& cur(pdf_ens_s* E) { return E->buf[E->cur]; }
+
+// group the particles of the current buffer by element, bin them, mix (mix != 0), write
 // canonical order into the other buffer and reduce the statistics
-pdf_status regroup(pdf_ens_s* E, double dt, bool counts_ready, hipStream_t s)
+template <class R>
+pdf_status regroup(pdf_ens_s* E, bool mix, bool counts_ready, bool advance_step, hipStream_t s)
 {
-    pdf_grid_s* g = E->grid;
-    Soa& in = cur(E);
+    DevGrid& g = E->dg;
+    SoaRaw& in = cur(E);
     if (!counts_ready) {
         Timed t(E, T_COUNT, s);
-        launch_count(in.elem, E->d_meta, E->n_slots_ub, g->ne, E->counts, E->err, s);
+        launch_count(in.elem, E->d_meta, E->n_slots_ub, g.ne, E->counts, E->err, s);
     }
     {
         Timed t(E, T_SCAN, s);
-        launch_scan(E->counts, g->ne, E->start, E->scan_tmp, s);
+        launch_scan(E->counts, g.ne, E->start, E->scan_tmp, s);
     }
     {
         Timed t(E, T_SCATTER, s);
-        launch_scatter(in.elem, E->d_meta, E->n_slots_ub, g->ne, E->counts, E->start, E->idx, E->err, s);
+        launch_scatter(in.elem, E->d_meta, E->n_slots_ub, g.ne, E->counts, E->start, E->idx, E->err, s);
     }
-    ElementArgs ea{};
-    ea.in = in;
-    ea.out = E->buf[1 - E->cur];
+    ElementArgs<R> ea{};
+    ea.in = in.as<R>();
+    ea.out = E->buf[1 - E->cur].as<R>();
     ea.start = E->start;
     ea.idx = E->idx;
-    ea.geo = g->d_geo;
-    ea.shift = E->shift;
-    ea.part = E->part;
+    ea.geo = g.geo;
+    ea.prm = E->d_prm;
+    ea.shift = static_cast<const R*>(E->shift);
+    ea.part = static_cast<R*>(E->part);
     ea.tm = E->tm;
-    ea.dt = dt;
-    ea.ne = g->ne;
+    ea.mix = mix ? 1 : 0;
+    ea.ne = g.ne;
     ea.cap = E->cap;
-    ea.bins0 = E->d.bins[0];
-    ea.bins1 = E->d.bins[1];
-    ea.bins2 = E->d.bins[2];
-    ea.minpb = E->d.min_per_bin;
     ea.lds_max = E->lds_max;
     ea.ppl = E->ppl;
     ea.big_list = E->big_list;
@@ -151,25 +150,362 @@ pdf_status regroup(pdf_ens_s* E, double dt, bool counts_ready, hipStream_t s)
     ea.gu3 = E->gu3;
     {
         Timed t(E, T_ELEMENT, s);
-        launch_element_pass(ea, s);
+        launch_element_pass<R>(ea, s);
     }
-    NodeArgs na{};
-    na.part = E->part;
-    na.n2e_ptr = g->d_n2e_ptr;
-    na.n2e = g->d_n2e;
-    na.shift = E->shift;
+    NodeArgs<R> na{};
+    na.part = static_cast<const R*>(E->part);
+    na.n2e_ptr = g.n2e_ptr;
+    na.n2e = g.n2e;
+    na.shift = static_cast<R*>(E->shift);
     na.stats = E->stats;
-    na.nn = g->nn;
+    na.nn = g.nn;
     na.start = E->start;
-    na.ne = g->ne;
+    na.ne = g.ne;
     na.meta = E->d_meta;
     na.big_count = E->big_count;
+    na.advance_step = advance_step ? 1 : 0;
     {
         Timed t(E, T_NODE, s);
-        launch_node_finalize(na, s);
+        launch_node_finalize<R>(na, s);
     }
     E->cur = 1 - E->cur;
     HIP_TRY(hipGetLastError());
+    return PDF_OK;
+}
+
+pdf_status regroup_any(pdf_ens_s* E, bool mix, bool counts_ready, bool advance_step, hipStream_t s)
+{
+    return E->precision == PDF_MIXED ? regroup<float>(E, mix, counts_ready, advance_step, s)
+                                     : regroup<double>(E, mix, counts_ready, advance_step, s);
+}
+
+// one time step: particle loop, then grouping, binning, mixing and statistics
+template <class R>
+pdf_status step_once(pdf_ens_s* E, hipStream_t s)
+{
+    DevGrid& g = E->dg;
+    AdvanceArgs<R> a{};
+    a.s = cur(E).as<R>();
+    a.geo = g.geo;
+    a.node = E->precision == PDF_MIXED ? reinterpret_cast<const R*>(g.node32) : reinterpret_cast<const R*>(g.node);
+    a.n2e_ptr = g.n2e_ptr;
+    a.n2e = g.n2e;
+    a.counts = E->counts;
+    a.err = E->err;
+    a.cnt = E->cnt;
+    a.meta = E->d_meta;
+    a.ne = g.ne;
+    a.p0 = E->h_prm[0];
+    a.prm = E->d_prm;
+    {
+        Timed t(E, T_ADVANCE, s);
+        launch_advance<R>(a, E->n_slots_ub, E->n_problems > 1, E->adv_block, s);
+    }
+    HIP_TRY(hipGetLastError());
+    pdf_status st = regroup<R>(E, true, true, true, s);
+    if (st != PDF_OK) return st;
+    E->step += 1;
+    return PDF_OK;
+}
+
+pdf_status step_any(pdf_ens_s* E, hipStream_t s)
+{
+    return E->precision == PDF_MIXED ? step_once<float>(E, s) : step_once<double>(E, s);
+}
+
+// upload the per-problem time steps when they changed
+pdf_status set_dt(pdf_ens_s* E, const double* dt, hipStream_t s)
+{
+    bool changed = false;
+    for (int p = 0; p < E->n_problems; ++p)
+        if (E->h_prm[p].dt != dt[p]) {
+            E->h_prm[p].dt = dt[p];
+            changed = true;
+        }
+    if (changed)
+        HIP_TRY(hipMemcpyAsync(E->d_prm, E->h_prm.data(), sizeof(ProbParams) * E->n_problems,
+                               hipMemcpyHostToDevice, s));
+    if (changed) HIP_TRY(hipStreamSynchronize(s));   // the host table may change again
+    return PDF_OK;
+}
+
+void drop_graphs(pdf_ens_s* E)
+{
+    for (int c = 0; c < 2; ++c) {
+        if (E->gexec[c]) (void)hipGraphExecDestroy(E->gexec[c]);
+        E->gexec[c] = nullptr;
+        E->g_nub[c] = -1;
+        E->g_dt[c].clear();
+    }
+}
+
+// Two steps from buffer c captured once into a HIP graph and replayed; captured again when
+// the slot bound (after number control) or a time step changes.
+pdf_status graph_steps(pdf_ens_s* E, int32_t n_steps, hipStream_t s)
+{
+    if (!E->gstream) {
+        HIP_TRY(hipStreamCreateWithFlags(&E->gstream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&E->gev[0], hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&E->gev[1], hipEventDisableTiming));
+    }
+    hipStream_t gs = E->gstream;
+    HIP_TRY(hipEventRecord(E->gev[0], s));
+    HIP_TRY(hipStreamWaitEvent(gs, E->gev[0], 0));
+    std::vector<double> dts(E->n_problems);
+    for (int p = 0; p < E->n_problems; ++p) dts[p] = E->h_prm[p].dt;
+    int32_t left = n_steps;
+    while (left >= 2) {
+        const int c = E->cur;
+        if (!E->gexec[c] || E->g_nub[c] != E->n_slots_ub || E->g_dt[c] != dts) {
+            if (E->gexec[c]) (void)hipGraphExecDestroy(E->gexec[c]);
+            E->gexec[c] = nullptr;
+            const int64_t step0 = E->step;
+            HIP_TRY(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+            E->capturing = true;
+            pdf_status st = step_any(E, gs);
+            if (st == PDF_OK) st = step_any(E, gs);
+            E->capturing = false;
+            hipGraph_t graph = nullptr;
+            const hipError_t ce = hipStreamEndCapture(gs, &graph);
+            E->step = step0;
+            if (st != PDF_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            HIP_TRY(ce);
+            const hipError_t ie = hipGraphInstantiate(&E->gexec[c], graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIP_TRY(ie);
+            E->g_nub[c] = E->n_slots_ub;
+            E->g_dt[c] = dts;
+        }
+        HIP_TRY(hipGraphLaunch(E->gexec[c], gs));
+        E->step += 2;
+        left -= 2;
+    }
+    if (left) {
+        pdf_status st = step_any(E, gs);
+        if (st != PDF_OK) return st;
+    }
+    HIP_TRY(hipEventRecord(E->gev[1], gs));
+    HIP_TRY(hipStreamWaitEvent(s, E->gev[1], 0));
+    return PDF_OK;
+}
+
+template <class R>
+pdf_status control_impl(pdf_ens_s* E, int32_t n_min, int32_t n_max, pdf_control_report* report, hipStream_t s)
+{
+    DevGrid& g = E->dg;
+    launch_fill_u64(E->ctl_rep, 4, 0ull, s);
+    ControlArgs<R> c{};
+    c.s = cur(E).as<R>();
+    c.start = E->start;
+    c.geo = g.geo;
+    c.prm = E->d_prm;
+    c.n_problems = E->n_problems;
+    c.clone = E->ctl_clone;
+    c.off = E->ctl_off;
+    c.rep = E->ctl_rep;
+    c.err = E->err;
+    c.nslots = E->d_meta;
+    c.ne = g.ne;
+    c.cap = E->cap;
+    c.n_min = n_min;
+    c.n_max = n_max;
+    {
+        Timed t(E, T_CPLAN, s);
+        launch_ctl_plan<R>(c, s);
+    }
+    {
+        Timed t(E, T_CSCAN, s);
+        launch_scan(E->ctl_clone, g.ne, E->ctl_off, E->scan_tmp, s);
+    }
+    {
+        Timed t(E, T_CAPPLY, s);
+        launch_ctl_apply<R>(c, s);
+        launch_ctl_finish(E->d_meta, E->ctl_off, g.ne, E->ctl_rep, E->cap, E->d_prm, E->n_problems, s);
+    }
+    HIP_TRY(hipGetLastError());
+    int64_t meta[3];
+    unsigned long long rep[4];
+    HIP_TRY(hipMemcpyAsync(meta, E->d_meta, sizeof(meta), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(rep, E->ctl_rep, sizeof(rep), hipMemcpyDeviceToHost, s));
+    std::vector<ProbParams> prm(E->n_problems);
+    HIP_TRY(hipMemcpyAsync(prm.data(), E->d_prm, sizeof(ProbParams) * E->n_problems, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int p = 0; p < E->n_problems; ++p) E->h_prm[p].next_pid = prm[p].next_pid;
+    E->n_slots_ub = meta[0];
+    E->ctl_valid = false;
+    if (report) {
+        report->live = meta[1];
+        report->cloned = meta[2];
+        report->merged = (int64_t)rep[0];
+        report->empty = (int64_t)rep[1];
+        report->below = (int64_t)rep[2];
+        report->above = (int64_t)rep[3];
+    }
+    return check_device_error(E);
+}
+
+void free_devgrid(DevGrid& g)
+{
+    if (g.owned) {
+        dfree(g.geo);
+        dfree(g.node);
+        dfree(g.n2e_ptr);
+        dfree(g.n2e);
+    }
+    dfree(g.node32);
+    g = DevGrid{};
+}
+
+// device grid of the ensemble: the grid itself for one problem, concatenated copies with
+// offset element, node and CSR indices for several
+pdf_status build_devgrid(pdf_ens_s* E, hipStream_t s)
+{
+    DevGrid& d = E->dg;
+    const int P = E->n_problems;
+    if (P == 1) {
+        pdf_grid_s* g = E->grids[0];
+        d.nn = g->nn;
+        d.ne = g->ne;
+        d.geo = g->d_geo;
+        d.node = g->d_node;
+        d.n2e_ptr = g->d_n2e_ptr;
+        d.n2e = g->d_n2e;
+        d.owned = false;
+    } else {
+        int64_t nn = 0, ne = 0;
+        for (auto* g : E->grids) {
+            nn += g->nn;
+            ne += g->ne;
+        }
+        std::vector<ElemGeo> geo;
+        std::vector<double> node;
+        std::vector<int64_t> ptr(1, 0);
+        std::vector<int32_t> n2e;
+        geo.reserve(ne);
+        node.reserve(nn * NODE_STRIDE);
+        n2e.reserve(3 * ne);
+        int64_t eo = 0, no = 0;
+        for (int p = 0; p < P; ++p) {
+            const pdf_grid_s* g = E->grids[p];
+            for (const ElemGeo& G0 : g->h_geo) {
+                ElemGeo G = G0;
+                for (int k = 0; k < 3; ++k) {
+                    G.node[k] += (int32_t)no;
+                    if (G.nbr[k] >= 0) G.nbr[k] += (int32_t)eo;
+                }
+                G.prob = p;
+                geo.push_back(G);
+            }
+            node.insert(node.end(), g->h_node.begin(), g->h_node.end());
+            const int64_t base = (int64_t)n2e.size();
+            for (int64_t i = 0; i < g->nn; ++i) ptr.push_back(base + g->h_n2e_ptr[i + 1]);
+            for (int32_t v : g->h_n2e) n2e.push_back(v + 3 * (int32_t)eo);
+            eo += g->ne;
+            no += g->nn;
+        }
+        d.nn = nn;
+        d.ne = ne;
+        d.owned = true;
+        pdf_status st = dalloc(&d.geo, ne);
+        if (st == PDF_OK) st = dalloc(&d.node, nn * NODE_STRIDE);
+        if (st == PDF_OK) st = dalloc(&d.n2e_ptr, nn + 1);
+        if (st == PDF_OK) st = dalloc(&d.n2e, 3 * ne);
+        if (st != PDF_OK) return st;
+        HIP_TRY(hipMemcpyAsync(d.geo, geo.data(), sizeof(ElemGeo) * ne, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d.node, node.data(), sizeof(double) * nn * NODE_STRIDE, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d.n2e_ptr, ptr.data(), sizeof(int64_t) * (nn + 1), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d.n2e, n2e.data(), sizeof(int32_t) * 3 * ne, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    if (E->precision == PDF_MIXED) {
+        pdf_status st = dalloc(&d.node32, d.nn * NODE_STRIDE);
+        if (st != PDF_OK) return st;
+        launch_f64_to_f32(d.node, d.node32, d.nn * NODE_STRIDE, s);
+    }
+    return PDF_OK;
+}
+
+// bytes of one state array entry other than x, y, pid, elem
+size_t real_size(const pdf_ens_s* E) { return E->precision == PDF_MIXED ? sizeof(float) : sizeof(double); }
+
+pdf_status alloc_raw(void** p, int64_t count, size_t elem)
+{
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    hipError_t e = hipMalloc(p, elem * (size_t)count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        set_error(std::string("device allocation of ") + std::to_string(elem * count) + " bytes failed");
+        return PDF_E_NOMEM;
+    }
+    return PDF_OK;
+}
+
+void free_raw(void*& p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+template <class R>
+void launch_init_any(pdf_ens_s* E, int64_t n0, hipStream_t s)
+{
+    InitArgs<R> ia{};
+    ia.s = E->buf[0].as<R>();
+    ia.geo = E->dg.geo;
+    ia.node = E->precision == PDF_MIXED ? reinterpret_cast<const R*>(E->dg.node32)
+                                        : reinterpret_cast<const R*>(E->dg.node);
+    ia.prm = E->d_prm;
+    ia.n_problems = E->n_problems;
+    ia.n = n0;
+    launch_init<R>(ia, s);
+}
+
+template <class R>
+pdf_status setup_precision(pdf_ens_s* E, hipStream_t s)
+{
+    const int fixed = (int)element_pass_smem<R>(0);
+    const int per = (int)element_pass_smem<R>(1) - fixed;
+    E->lds_max = std::max(64, (65536 - fixed) / per);
+    HIP_TRY(prepare_element_pass<R>(E->lds_max));
+    const R* node = E->precision == PDF_MIXED ? reinterpret_cast<const R*>(E->dg.node32)
+                                              : reinterpret_cast<const R*>(E->dg.node);
+    launch_shift_init<R>(node, E->dg.nn, static_cast<R*>(E->shift), s);
+    return PDF_OK;
+}
+
+// device-to-host copy of one state array of the current buffer, as doubles
+pdf_status pull_real(pdf_ens_s* E, const void* src, int64_t ns, std::vector<double>& out)
+{
+    out.resize(ns);
+    if (ns == 0) return PDF_OK;
+    if (E->precision == PDF_MIXED) {
+        std::vector<float> t(ns);
+        HIP_TRY(hipMemcpy(t.data(), src, sizeof(float) * ns, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < ns; ++i) out[i] = (double)t[i];
+    } else {
+        HIP_TRY(hipMemcpy(out.data(), src, sizeof(double) * ns, hipMemcpyDeviceToHost));
+    }
+    return PDF_OK;
+}
+
+pdf_status push_real(pdf_ens_s* E, void* dst, const std::vector<double>& in, hipStream_t s)
+{
+    const int64_t n = (int64_t)in.size();
+    if (n == 0) return PDF_OK;
+    if (E->precision == PDF_MIXED) {
+        std::vector<float> t(n);
+        for (int64_t i = 0; i < n; ++i) t[i] = (float)in[i];
+        HIP_TRY(hipMemcpyAsync(dst, t.data(), sizeof(float) * n, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    } else {
+        HIP_TRY(hipMemcpyAsync(dst, in.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     return PDF_OK;
 }
 
@@ -252,15 +588,20 @@ pdf_status pdf_ens_destroy(pdf_ens E)
         (void)hipEventDestroy(ev.second.first);
         (void)hipEventDestroy(ev.second.second);
     }
+    drop_graphs(E);
+    if (E->gstream) (void)hipStreamDestroy(E->gstream);
+    for (int k = 0; k < 2; ++k)
+        if (E->gev[k]) (void)hipEventDestroy(E->gev[k]);
     for (int b = 0; b < 2; ++b) {
-        Soa& S = E->buf[b];
-        dfree(S.x); dfree(S.y); dfree(S.u0); dfree(S.u1); dfree(S.u2); dfree(S.om); dfree(S.psi); dfree(S.w);
-        dfree(S.pid); dfree(S.elem);
+        SoaRaw& S = E->buf[b];
+        dfree(S.x); dfree(S.y); free_raw(S.u0); free_raw(S.u1); free_raw(S.u2); free_raw(S.om); free_raw(S.psi);
+        free_raw(S.w); dfree(S.pid); dfree(S.elem);
     }
-    dfree(E->counts); dfree(E->start); dfree(E->idx); dfree(E->scan_tmp); dfree(E->d_meta); dfree(E->part);
-    dfree(E->stats); dfree(E->shift); dfree(E->tm); dfree(E->err); dfree(E->cnt); dfree(E->gkey); dfree(E->gord);
+    dfree(E->counts); dfree(E->start); dfree(E->idx); dfree(E->scan_tmp); dfree(E->d_meta); free_raw(E->part);
+    dfree(E->stats); free_raw(E->shift); dfree(E->tm); dfree(E->err); dfree(E->cnt); dfree(E->gkey); dfree(E->gord);
     dfree(E->gu3); dfree(E->ctl_clone); dfree(E->ctl_off); dfree(E->ctl_rep); dfree(E->big_list);
-    dfree(E->big_count);
+    dfree(E->big_count); dfree(E->d_prm); dfree(E->d_scalar);
+    free_devgrid(E->dg);
     delete E;
     return PDF_OK;
 }
@@ -268,99 +609,150 @@ pdf_status pdf_ens_destroy(pdf_ens E)
 pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs, int32_t n_problems,
                               void* hip_stream, pdf_ens* out)
 {
-    if (!grids || !descs || !out || !grids[0]) {
-        set_error("pdf_particles_init: null argument");
+    if (!grids || !descs || !out || n_problems < 1) {
+        set_error("pdf_particles_init: null argument or n_problems < 1");
         return PDF_E_INVAL;
     }
     *out = nullptr;
-    if (n_problems != 1) {
-        set_error("pdf_particles_init: n_problems must be 1");
-        return PDF_E_INVAL;
+    int64_t n0 = 0, ne = 0, cap = 0;
+    for (int p = 0; p < n_problems; ++p) {
+        const pdf_init_desc& d = descs[p];
+        const pdf_grid_s* g = grids[p];
+        if (!g) {
+            set_error("pdf_particles_init: null grid");
+            return PDF_E_INVAL;
+        }
+        const int64_t nb = (int64_t)d.bins[0] * d.bins[1] * d.bins[2];
+        if (d.ppe < 0 || d.bins[0] < 1 || d.bins[1] < 1 || d.bins[2] < 1 || nb > MAXBINS || d.min_per_bin < 1 ||
+            !(d.omega_shape >= 1.0) || !(d.u_sigma >= 0.0) || !(d.src_r >= 0.0) || !std::isfinite(d.u_sigma) ||
+            !std::isfinite(d.omega_shape) || !std::isfinite(d.src_x) || !std::isfinite(d.src_y) ||
+            !std::isfinite(d.src_r) || (d.precision != PDF_FP64 && d.precision != PDF_MIXED) ||
+            d.precision != descs[0].precision || d.capacity < 0 || g->device != grids[0]->device) {
+            set_error("pdf_particles_init: invalid descriptor (bins product <= 1024, omega_shape >= 1, one "
+                      "precision and one device for all problems)");
+            return PDF_E_INVAL;
+        }
+        const int64_t n0p = g->ne * (int64_t)d.ppe;
+        n0 += n0p;
+        ne += g->ne;
+        cap += d.capacity > 0 ? d.capacity : std::max<int64_t>(2 * n0p, 1024);
+        if (d.capacity > 0 && d.capacity < n0p) {
+            set_error("pdf_particles_init: capacity below the initial particle count");
+            return PDF_E_CAPACITY;
+        }
     }
-    const pdf_init_desc& d = descs[0];
-    pdf_grid_s* g = grids[0];
-    const int64_t nb = (int64_t)d.bins[0] * d.bins[1] * d.bins[2];
-    if (d.ppe < 0 || d.bins[0] < 1 || d.bins[1] < 1 || d.bins[2] < 1 || nb > MAXBINS || d.min_per_bin < 1 ||
-        !(d.omega_shape >= 1.0) || !(d.u_sigma >= 0.0) || !(d.src_r >= 0.0) || !std::isfinite(d.u_sigma) ||
-        !std::isfinite(d.omega_shape) || !std::isfinite(d.src_x) || !std::isfinite(d.src_y) ||
-        !std::isfinite(d.src_r) || d.precision != 0 || d.capacity < 0) {
-        set_error("pdf_particles_init: invalid descriptor (bins product <= 1024, omega_shape >= 1, precision 0)");
-        return PDF_E_INVAL;
-    }
-    if (g->ne > scan_max_elems()) {
+    if (ne > scan_max_elems() || ne > (int64_t)INT32_MAX / 3) {
         set_error("pdf_particles_init: too many elements for the segment scan");
         return PDF_E_INVAL;
-    }
-    const int64_t n0 = g->ne * (int64_t)d.ppe;
-    int64_t cap = d.capacity > 0 ? d.capacity : std::max<int64_t>(2 * n0, 1024);
-    if (cap < n0) {
-        set_error("pdf_particles_init: capacity below the initial particle count");
-        return PDF_E_CAPACITY;
     }
     if (cap > (int64_t)INT32_MAX - 1) {
         set_error("pdf_particles_init: capacity above 2^31 - 2 slots");
         return PDF_E_INVAL;
     }
-    HIP_TRY(hipSetDevice(g->device));
+    pdf_grid_s* g0 = grids[0];
+    HIP_TRY(hipSetDevice(g0->device));
     hipStream_t s = as_stream(hip_stream);
     pdf_ens_s* E = new pdf_ens_s();
-    E->grid = g;
-    E->d = d;
+    E->grid = g0;
+    E->grids.assign(grids, grids + n_problems);
+    E->descs.assign(descs, descs + n_problems);
+    E->n_problems = n_problems;
+    E->precision = descs[0].precision;
+    E->d = descs[0];
     E->cap = cap;
     E->stream = s;
-    E->next_pid = (uint64_t)n0;
-    pdf_status st = PDF_OK;
+    pdf_status st = build_devgrid(E, s);
+    // per-problem parameter table
+    {
+        int64_t eo = 0, no = 0, so = 0;
+        for (int p = 0; p < n_problems && st == PDF_OK; ++p) {
+            const pdf_init_desc& d = descs[p];
+            const pdf_grid_s* g = grids[p];
+            ProbParams P{};
+            P.m = g->model;
+            P.dt = 0.0;
+            P.period = g->period;
+            P.src_x = d.src_x;
+            P.src_y = d.src_y;
+            P.src_r2 = d.src_r * d.src_r;
+            P.u_sigma = d.u_sigma;
+            P.omega_shape = d.omega_shape;
+            P.key = RngKey{(uint32_t)d.seed, (uint32_t)(d.seed >> 32) ^ (uint32_t)p};
+            P.src_cont = d.src_continuous;
+            P.bins0 = d.bins[0];
+            P.bins1 = d.bins[1];
+            P.bins2 = d.bins[2];
+            P.minpb = d.min_per_bin;
+            P.ppe = d.ppe > 0 ? d.ppe : 1;
+            P.eoff = eo;
+            P.ne = g->ne;
+            P.noff = no;
+            P.nn = g->nn;
+            P.soff = so;
+            P.next_pid = (uint64_t)(g->ne * (int64_t)d.ppe);
+            E->h_prm.push_back(P);
+            eo += g->ne;
+            no += g->nn;
+            so += g->ne * (int64_t)d.ppe;
+        }
+    }
+    const size_t rs = real_size(E);
     for (int b = 0; b < 2 && st == PDF_OK; ++b) {
-        Soa& S = E->buf[b];
+        SoaRaw& S = E->buf[b];
         st = dalloc(&S.x, cap);
         if (st == PDF_OK) st = dalloc(&S.y, cap);
-        if (st == PDF_OK) st = dalloc(&S.u0, cap);
-        if (st == PDF_OK) st = dalloc(&S.u1, cap);
-        if (st == PDF_OK) st = dalloc(&S.u2, cap);
-        if (st == PDF_OK) st = dalloc(&S.om, cap);
-        if (st == PDF_OK) st = dalloc(&S.psi, cap);
-        if (st == PDF_OK) st = dalloc(&S.w, cap);
+        if (st == PDF_OK) st = alloc_raw(&S.u0, cap, rs);
+        if (st == PDF_OK) st = alloc_raw(&S.u1, cap, rs);
+        if (st == PDF_OK) st = alloc_raw(&S.u2, cap, rs);
+        if (st == PDF_OK) st = alloc_raw(&S.om, cap, rs);
+        if (st == PDF_OK) st = alloc_raw(&S.psi, cap, rs);
+        if (st == PDF_OK) st = alloc_raw(&S.w, cap, rs);
         if (st == PDF_OK) st = dalloc(&S.pid, cap);
         if (st == PDF_OK) st = dalloc(&S.elem, cap);
     }
-    if (st == PDF_OK) st = dalloc(&E->counts, g->ne);
-    if (st == PDF_OK) st = dalloc(&E->start, g->ne + 1);
+    const DevGrid& g = E->dg;
+    if (st == PDF_OK) st = dalloc(&E->d_prm, n_problems);
+    if (st == PDF_OK) st = dalloc(&E->counts, g.ne);
+    if (st == PDF_OK) st = dalloc(&E->start, g.ne + 1);
     if (st == PDF_OK) st = dalloc(&E->idx, cap);
-    if (st == PDF_OK) st = dalloc(&E->scan_tmp, scan_blocks(g->ne) + 1);
+    if (st == PDF_OK) st = dalloc(&E->scan_tmp, scan_blocks(g.ne) + 1);
     if (st == PDF_OK) st = dalloc(&E->d_meta, 8);
-    if (st == PDF_OK) st = dalloc(&E->part, g->ne * 3 * NPART);
-    if (st == PDF_OK) st = dalloc(&E->stats, g->nn * NSTAT);
-    if (st == PDF_OK) st = dalloc(&E->shift, g->nn * 5);
-    if (st == PDF_OK) st = dalloc(&E->tm, g->ne);
+    if (st == PDF_OK) st = alloc_raw(&E->part, g.ne * 3 * NPART, rs);
+    if (st == PDF_OK) st = dalloc(&E->stats, g.nn * NSTAT);
+    if (st == PDF_OK) st = alloc_raw(&E->shift, g.nn * 5, rs);
+    if (st == PDF_OK) st = dalloc(&E->tm, g.ne);
     if (st == PDF_OK) st = dalloc(&E->err, 1);
-    if (st == PDF_OK) st = dalloc(&E->cnt, NCOUNT * CNT_SLOTS);
+    if (st == PDF_OK) st = dalloc(&E->cnt, (int64_t)n_problems * NCOUNT * CNT_SLOTS);
+    if (st == PDF_OK) st = dalloc(&E->d_scalar, 8);
     if (st == PDF_OK) st = dalloc(&E->gkey, 2 * cap);
     if (st == PDF_OK) st = dalloc(&E->gord, 2 * cap);
     if (st == PDF_OK) st = dalloc(&E->gu3, 4 * cap);
-    if (st == PDF_OK) st = dalloc(&E->ctl_clone, g->ne);
-    if (st == PDF_OK) st = dalloc(&E->ctl_off, g->ne + 1);
+    if (st == PDF_OK) st = dalloc(&E->ctl_clone, g.ne);
+    if (st == PDF_OK) st = dalloc(&E->ctl_off, g.ne + 1);
     if (st == PDF_OK) st = dalloc(&E->ctl_rep, 4);
-    if (st == PDF_OK) st = dalloc(&E->big_list, g->ne);
+    if (st == PDF_OK) st = dalloc(&E->big_list, g.ne);
     if (st == PDF_OK) st = dalloc(&E->big_count, 1);
     if (st != PDF_OK) {
         pdf_ens_destroy(E);
         return st;
     }
     // element pass: a wavefront per element holds up to 64 * ppl particles (ppl from the
-    // set-up count with 30 % headroom); larger elements go to the workgroup kernel, whose
-    // on-chip path takes up to lds_max particles within 64 KiB of LDS
-    E->ppl = (int)std::min<int64_t>(8, std::max<int64_t>(1, (13 * (int64_t)d.ppe + 639) / 640));
+    // largest set-up count with 30 % headroom); larger elements go to the workgroup
+    // kernel, whose on-chip path takes up to lds_max particles within 64 KiB of LDS
+    int64_t ppe_max = 1;
+    for (auto& d : E->descs) ppe_max = std::max<int64_t>(ppe_max, d.ppe);
+    E->ppl = (int)std::min<int64_t>(8, std::max<int64_t>(1, (13 * ppe_max + 639) / 640));
     if (E->ppl == 7) E->ppl = 8;
-    {
-        const int fixed = (int)element_pass_smem(0);
-        const int per = (int)element_pass_smem(1) - fixed;
-        E->lds_max = std::max(64, (65536 - fixed) / per);
-        HIP_TRY(prepare_element_pass(E->lds_max));
+    HIP_TRY(hipMemcpyAsync(E->d_prm, E->h_prm.data(), sizeof(ProbParams) * n_problems, hipMemcpyHostToDevice, s));
+    st = E->precision == PDF_MIXED ? setup_precision<float>(E, s) : setup_precision<double>(E, s);
+    if (st != PDF_OK) {
+        pdf_ens_destroy(E);
+        return st;
     }
-    launch_fill_i32(E->counts, g->ne, 0, s);
+    launch_fill_i32(E->counts, g.ne, 0, s);
     launch_fill_i32(E->big_count, 1, 0, s);
     launch_fill_i32(E->idx, cap, 0, s);
-    launch_fill_u64(E->cnt, NCOUNT * CNT_SLOTS, 0ull, s);
+    launch_fill_u64(E->cnt, (int64_t)n_problems * NCOUNT * CNT_SLOTS, 0ull, s);
     launch_fill_i32(reinterpret_cast<int32_t*>(E->err), 1, 0, s);
     launch_fill_i32(E->buf[0].elem, cap, -1, s);
     launch_fill_i32(E->buf[1].elem, cap, -1, s);
@@ -369,28 +761,15 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
     meta[1] = n0;
     HIP_TRY(hipMemcpyAsync(E->d_meta, meta.data(), sizeof(int64_t) * 8, hipMemcpyHostToDevice, s));
     E->n_slots_ub = n0;
-    launch_shift_init(g->d_node, g->nn, E->shift, s);
-    launch_tm(g->d_geo, g->d_node, g->ne, g->model, d.src_x, d.src_y, d.src_r, g->period, E->tm, s);
-    InitArgs ia{};
-    ia.s = E->buf[0];
-    ia.geo = g->d_geo;
-    ia.node = g->d_node;
-    ia.n = n0;
-    ia.ppe = d.ppe;
-    ia.key = RngKey{(uint32_t)d.seed, (uint32_t)(d.seed >> 32) ^ (uint32_t)E->problem};
-    ia.u_sigma = d.u_sigma;
-    ia.omega_shape = d.omega_shape;
-    ia.src_x = d.src_x;
-    ia.src_y = d.src_y;
-    ia.src_r2 = d.src_r * d.src_r;
-    ia.period = g->period;
+    launch_tm(g.geo, g.node, g.ne, E->d_prm, E->tm, s);
     E->cur = 0;
     {
         Timed t(E, T_INIT, s);
-        launch_init(ia, s);
+        if (E->precision == PDF_MIXED) launch_init_any<float>(E, n0, s);
+        else launch_init_any<double>(E, n0, s);
     }
     HIP_TRY(hipGetLastError());
-    st = regroup(E, 0.0, false, s);
+    st = regroup_any(E, false, false, false, s);
     if (st != PDF_OK) {
         pdf_ens_destroy(E);
         return st;
@@ -413,46 +792,26 @@ pdf_status pdf_step(pdf_ens E, const double* dt, int32_t n_steps, void* hip_stre
         set_error("pdf_step: invalid argument");
         return PDF_E_INVAL;
     }
-    const double h = dt[0];
-    if (!(h > 0.0) || !std::isfinite(h)) {
-        set_error("pdf_step: dt must be positive and finite");
-        return PDF_E_INVAL;
-    }
-    pdf_grid_s* g = E->grid;
-    HIP_TRY(hipSetDevice(g->device));
+    for (int p = 0; p < E->n_problems; ++p)
+        if (!(dt[p] > 0.0) || !std::isfinite(dt[p])) {
+            set_error("pdf_step: dt must be positive and finite");
+            return PDF_E_INVAL;
+        }
+    HIP_TRY(hipSetDevice(E->grid->device));
     hipStream_t s = as_stream(hip_stream);
     E->stream = s;
-    for (int32_t it = 0; it < n_steps; ++it) {
-        AdvanceArgs a{};
-        a.s = cur(E);
-        a.geo = g->d_geo;
-        a.node = g->d_node;
-        a.n2e_ptr = g->d_n2e_ptr;
-        a.n2e = g->d_n2e;
-        a.counts = E->counts;
-        a.err = E->err;
-        a.cnt = E->cnt;
-        a.nslots = E->d_meta;
-        a.ne = g->ne;
-        a.period = g->period;
-        a.m = g->model;
-        a.dt = h;
-        a.key = RngKey{(uint32_t)E->d.seed, (uint32_t)(E->d.seed >> 32) ^ (uint32_t)E->problem};
-        a.step = (uint32_t)E->step;
-        a.src_x = E->d.src_x;
-        a.src_y = E->d.src_y;
-        a.src_r2 = E->d.src_r * E->d.src_r;
-        a.src_cont = E->d.src_continuous;
-        {
-            Timed t(E, T_ADVANCE, s);
-            launch_advance(a, E->n_slots_ub, s);
-        }
-        HIP_TRY(hipGetLastError());
-        pdf_status st = regroup(E, h, true, s);
+    pdf_status st = set_dt(E, dt, s);
+    if (st != PDF_OK) return st;
+    if (E->use_graph && n_steps > 0) {
+        st = graph_steps(E, n_steps, s);
         if (st != PDF_OK) return st;
-        E->step += 1;
+    } else {
+        for (int32_t it = 0; it < n_steps; ++it) {
+            st = step_any(E, s);
+            if (st != PDF_OK) return st;
+        }
     }
-    E->ctl_valid = true;   // canonical order of the last element pass
+    if (n_steps > 0) E->ctl_valid = true;   // canonical order of the last element pass
     return PDF_OK;
 }
 
@@ -469,33 +828,21 @@ pdf_status pdf_sync(pdf_ens E)
 
 pdf_status pdf_stats(pdf_ens E, int32_t problem, double* out, int32_t out_is_device, void* hip_stream)
 {
-    if (!E || !out || problem != 0) {
+    if (!E || !out || problem < 0 || problem >= E->n_problems) {
         set_error("pdf_stats: invalid argument");
         return PDF_E_INVAL;
     }
     HIP_TRY(hipSetDevice(E->grid->device));
     hipStream_t s = as_stream(hip_stream);
-    const size_t bytes = sizeof(double) * (size_t)E->grid->nn * NSTAT;
+    const ProbParams& P = E->h_prm[problem];
+    const size_t bytes = sizeof(double) * (size_t)P.nn * NSTAT;
+    const double* src = E->stats + P.noff * NSTAT;
     if (out_is_device) {
-        HIP_TRY(hipMemcpyAsync(out, E->stats, bytes, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToDevice, s));
         return PDF_OK;
     }
-    HIP_TRY(hipMemcpyAsync(out, E->stats, bytes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    return check_device_error(E);
-}
-
-pdf_status pdf_count(pdf_ens E, int32_t problem, int64_t* live)
-{
-    if (!E || !live || problem != 0) {
-        set_error("pdf_count: invalid argument");
-        return PDF_E_INVAL;
-    }
-    HIP_TRY(hipSetDevice(E->grid->device));
-    HIP_TRY(hipStreamSynchronize(E->stream));
-    int64_t meta[2];
-    HIP_TRY(hipMemcpy(meta, E->d_meta, sizeof(meta), hipMemcpyDeviceToHost));
-    *live = meta[1];
     return check_device_error(E);
 }
 
@@ -505,62 +852,40 @@ pdf_status pdf_control(pdf_ens E, int32_t n_min, int32_t n_max, pdf_control_repo
         set_error("pdf_control: need 0 <= n_min <= n_max and n_max >= 1");
         return PDF_E_INVAL;
     }
-    pdf_grid_s* g = E->grid;
-    HIP_TRY(hipSetDevice(g->device));
+    HIP_TRY(hipSetDevice(E->grid->device));
     hipStream_t s = as_stream(hip_stream);
     E->stream = s;
     if (!E->ctl_valid) {
         set_error("pdf_control: no element pass since the last control");
         return PDF_E_STATE;
     }
-    launch_fill_u64(E->ctl_rep, 4, 0ull, s);
-    ControlArgs c{};
-    c.s = cur(E);
-    c.start = E->start;
-    c.clone = E->ctl_clone;
-    c.off = E->ctl_off;
-    c.rep = E->ctl_rep;
-    c.err = E->err;
-    c.nslots = E->d_meta;
-    c.ne = g->ne;
-    c.cap = E->cap;
-    c.n_min = n_min;
-    c.n_max = n_max;
-    c.bins0 = E->d.bins[0];
-    c.bins1 = E->d.bins[1];
-    c.bins2 = E->d.bins[2];
-    c.minpb = E->d.min_per_bin;
-    c.next_pid = E->next_pid;
-    {
-        Timed t(E, T_CPLAN, s);
-        launch_ctl_plan(c, s);
+    return E->precision == PDF_MIXED ? control_impl<float>(E, n_min, n_max, report, s)
+                                     : control_impl<double>(E, n_min, n_max, report, s);
+}
+
+pdf_status pdf_count(pdf_ens E, int32_t problem, int64_t* live)
+{
+    if (!E || !live || problem < -1 || problem >= E->n_problems) {
+        set_error("pdf_count: invalid argument");
+        return PDF_E_INVAL;
     }
-    {
-        Timed t(E, T_CSCAN, s);
-        launch_scan(E->ctl_clone, g->ne, E->ctl_off, E->scan_tmp, s);
+    HIP_TRY(hipSetDevice(E->grid->device));
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    if (problem == -1 || E->n_problems == 1) {
+        int64_t meta[2];
+        HIP_TRY(hipMemcpy(meta, E->d_meta, sizeof(meta), hipMemcpyDeviceToHost));
+        *live = meta[1];
+        return check_device_error(E);
     }
-    {
-        Timed t(E, T_CAPPLY, s);
-        launch_ctl_apply(c, s);
-        launch_ctl_finish(E->d_meta, E->ctl_off, g->ne, E->ctl_rep, E->cap, s);
-    }
-    HIP_TRY(hipGetLastError());
-    int64_t meta[3];
-    unsigned long long rep[4];
-    HIP_TRY(hipMemcpyAsync(meta, E->d_meta, sizeof(meta), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(rep, E->ctl_rep, sizeof(rep), hipMemcpyDeviceToHost, s));
+    const ProbParams& P = E->h_prm[problem];
+    hipStream_t s = E->stream;
+    launch_fill_u64(E->d_scalar, 1, 0ull, s);
+    launch_count_range(cur(E).elem, E->d_meta, E->n_slots_ub, (int32_t)P.eoff, (int32_t)(P.eoff + P.ne),
+                       E->d_scalar, s);
+    unsigned long long c = 0;
+    HIP_TRY(hipMemcpyAsync(&c, E->d_scalar, sizeof(c), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    E->n_slots_ub = meta[0];
-    E->next_pid += (uint64_t)meta[2];
-    E->ctl_valid = false;
-    if (report) {
-        report->live = meta[1];
-        report->cloned = meta[2];
-        report->merged = (int64_t)rep[0];
-        report->empty = (int64_t)rep[1];
-        report->below = (int64_t)rep[2];
-        report->above = (int64_t)rep[3];
-    }
+    *live = (int64_t)c;
     return check_device_error(E);
 }
 
@@ -568,7 +893,7 @@ pdf_status pdf_particles_export(pdf_ens E, int32_t problem, int64_t cap, double*
                                 double* omega, double* psi, double* w, uint64_t* pid, int32_t* elem, int64_t* n_out,
                                 void* hip_stream)
 {
-    if (!E || problem != 0 || cap < 0) {
+    if (!E || problem < 0 || problem >= E->n_problems || cap < 0) {
         set_error("pdf_particles_export: invalid argument");
         return PDF_E_INVAL;
     }
@@ -579,45 +904,64 @@ pdf_status pdf_particles_export(pdf_ens E, int32_t problem, int64_t cap, double*
     int64_t meta[2];
     HIP_TRY(hipMemcpy(meta, E->d_meta, sizeof(meta), hipMemcpyDeviceToHost));
     const int64_t ns = meta[0];
-    Soa& S = cur(E);
+    const ProbParams& P = E->h_prm[problem];
+    const int32_t lo = (int32_t)P.eoff, hi = (int32_t)(P.eoff + P.ne);
+    SoaRaw& S = cur(E);
     std::vector<int32_t> el(ns);
-    HIP_TRY(hipMemcpy(el.data(), S.elem, sizeof(int32_t) * ns, hipMemcpyDeviceToHost));
+    if (ns) HIP_TRY(hipMemcpy(el.data(), S.elem, sizeof(int32_t) * ns, hipMemcpyDeviceToHost));
     int64_t live = 0;
-    for (int64_t i = 0; i < ns; ++i) live += el[i] >= 0 ? 1 : 0;
+    for (int64_t i = 0; i < ns; ++i) live += (el[i] >= lo && el[i] < hi) ? 1 : 0;
     if (n_out) *n_out = live;
     if (live > cap) {
         set_error("pdf_particles_export: output capacity too small");
         return PDF_E_CAPACITY;
     }
-    std::vector<double> tmp(ns);
-    auto pull = [&](const double* src, double* dst, int stride, int comp) -> pdf_status {
-        if (!dst) return PDF_OK;
-        HIP_TRY(hipMemcpy(tmp.data(), src, sizeof(double) * ns, hipMemcpyDeviceToHost));
+    std::vector<double> tmp;
+    auto keep = [&](int64_t i) { return el[i] >= lo && el[i] < hi; };
+    auto put = [&](const std::vector<double>& src, double* dst, int stride, int comp) {
         int64_t j = 0;
         for (int64_t i = 0; i < ns; ++i)
-            if (el[i] >= 0) dst[stride * (j++) + comp] = tmp[i];
-        return PDF_OK;
+            if (keep(i)) dst[stride * (j++) + comp] = src[i];
     };
     pdf_status st;
-    if ((st = pull(S.x, x, 1, 0)) != PDF_OK) return st;
-    if ((st = pull(S.y, y, 1, 0)) != PDF_OK) return st;
-    if ((st = pull(S.u0, u, 3, 0)) != PDF_OK) return st;
-    if ((st = pull(S.u1, u, 3, 1)) != PDF_OK) return st;
-    if ((st = pull(S.u2, u, 3, 2)) != PDF_OK) return st;
-    if ((st = pull(S.om, omega, 1, 0)) != PDF_OK) return st;
-    if ((st = pull(S.psi, psi, 1, 0)) != PDF_OK) return st;
-    if ((st = pull(S.w, w, 1, 0)) != PDF_OK) return st;
+    if (x) {
+        tmp.resize(ns);
+        if (ns) HIP_TRY(hipMemcpy(tmp.data(), S.x, sizeof(double) * ns, hipMemcpyDeviceToHost));
+        put(tmp, x, 1, 0);
+    }
+    if (y) {
+        tmp.resize(ns);
+        if (ns) HIP_TRY(hipMemcpy(tmp.data(), S.y, sizeof(double) * ns, hipMemcpyDeviceToHost));
+        put(tmp, y, 1, 0);
+    }
+    const void* comps[3] = {S.u0, S.u1, S.u2};
+    for (int c = 0; c < 3 && u; ++c) {
+        if ((st = pull_real(E, comps[c], ns, tmp)) != PDF_OK) return st;
+        put(tmp, u, 3, c);
+    }
+    if (omega) {
+        if ((st = pull_real(E, S.om, ns, tmp)) != PDF_OK) return st;
+        put(tmp, omega, 1, 0);
+    }
+    if (psi) {
+        if ((st = pull_real(E, S.psi, ns, tmp)) != PDF_OK) return st;
+        put(tmp, psi, 1, 0);
+    }
+    if (w) {
+        if ((st = pull_real(E, S.w, ns, tmp)) != PDF_OK) return st;
+        put(tmp, w, 1, 0);
+    }
     if (pid) {
         std::vector<uint64_t> t(ns);
-        HIP_TRY(hipMemcpy(t.data(), S.pid, sizeof(uint64_t) * ns, hipMemcpyDeviceToHost));
+        if (ns) HIP_TRY(hipMemcpy(t.data(), S.pid, sizeof(uint64_t) * ns, hipMemcpyDeviceToHost));
         int64_t j = 0;
         for (int64_t i = 0; i < ns; ++i)
-            if (el[i] >= 0) pid[j++] = t[i];
+            if (keep(i)) pid[j++] = t[i];
     }
     if (elem) {
         int64_t j = 0;
         for (int64_t i = 0; i < ns; ++i)
-            if (el[i] >= 0) elem[j++] = el[i];
+            if (keep(i)) elem[j++] = el[i] - lo;
     }
     return check_device_error(E);
 }
@@ -627,17 +971,18 @@ pdf_status pdf_particles_import(pdf_ens E, int32_t problem, int64_t n, const dou
                                 const uint64_t* pid, const int32_t* elem, int64_t step, uint64_t next_pid,
                                 void* hip_stream)
 {
-    if (!E || problem != 0 || n < 0 || step < 0 || (n > 0 && (!x || !y || !u || !omega || !psi || !w || !pid || !elem))) {
-        set_error("pdf_particles_import: invalid argument");
+    if (!E || problem != 0 || E->n_problems != 1 || n < 0 || step < 0 ||
+        (n > 0 && (!x || !y || !u || !omega || !psi || !w || !pid || !elem))) {
+        set_error("pdf_particles_import: invalid argument (single-problem ensembles only)");
         return PDF_E_INVAL;
     }
     if (n > E->cap) {
         set_error("pdf_particles_import: more particles than capacity");
         return PDF_E_CAPACITY;
     }
-    pdf_grid_s* g = E->grid;
+    const DevGrid& g = E->dg;
     for (int64_t i = 0; i < n; ++i)
-        if (elem[i] < 0 || elem[i] >= g->ne) {
+        if (elem[i] < 0 || elem[i] >= g.ne) {
             set_error("pdf_particles_import: element index out of range");
             return PDF_E_INVAL;
         }
@@ -659,35 +1004,37 @@ pdf_status pdf_particles_import(pdf_ens E, int32_t problem, int64_t n, const dou
             set_error("pdf_particles_import: non-finite particle state");
             return PDF_E_NONFINITE;
         }
-    HIP_TRY(hipSetDevice(g->device));
+    HIP_TRY(hipSetDevice(E->grid->device));
     hipStream_t s = as_stream(hip_stream);
     E->stream = s;
     HIP_TRY(hipStreamSynchronize(s));
-    Soa& S = cur(E);
+    drop_graphs(E);
+    SoaRaw& S = cur(E);
     launch_fill_i32(S.elem, E->cap, -1, s);
     if (n > 0) {
+        pdf_status st;
         std::vector<double> c(n);
+        void* comps[3] = {S.u0, S.u1, S.u2};
         for (int comp = 0; comp < 3; ++comp) {
             for (int64_t i = 0; i < n; ++i) c[i] = u[3 * i + comp];
-            double* dst = comp == 0 ? S.u0 : (comp == 1 ? S.u1 : S.u2);
-            HIP_TRY(hipMemcpyAsync(dst, c.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
-            HIP_TRY(hipStreamSynchronize(s));
+            if ((st = push_real(E, comps[comp], c, s)) != PDF_OK) return st;
         }
+        if ((st = push_real(E, S.om, std::vector<double>(omega, omega + n), s)) != PDF_OK) return st;
+        if ((st = push_real(E, S.psi, std::vector<double>(psi, psi + n), s)) != PDF_OK) return st;
+        if ((st = push_real(E, S.w, std::vector<double>(w, w + n), s)) != PDF_OK) return st;
         HIP_TRY(hipMemcpyAsync(S.x, x, sizeof(double) * n, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(S.y, y, sizeof(double) * n, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(S.om, omega, sizeof(double) * n, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(S.psi, psi, sizeof(double) * n, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(S.w, w, sizeof(double) * n, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(S.pid, pid, sizeof(uint64_t) * n, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(S.elem, elem, sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
     }
-    int64_t meta[2] = {n, n};
+    int64_t meta[5] = {n, n, 0, 0, step};
     HIP_TRY(hipMemcpyAsync(E->d_meta, meta, sizeof(meta), hipMemcpyHostToDevice, s));
-    launch_fill_i32(E->counts, g->ne, 0, s);
+    launch_fill_i32(E->counts, g.ne, 0, s);
     E->n_slots_ub = n;
     E->step = step;
-    E->next_pid = next_pid;
-    pdf_status st = regroup(E, 0.0, false, s);
+    E->h_prm[0].next_pid = next_pid;
+    HIP_TRY(hipMemcpyAsync(E->d_prm, E->h_prm.data(), sizeof(ProbParams), hipMemcpyHostToDevice, s));
+    pdf_status st = regroup_any(E, false, false, false, s);
     if (st != PDF_OK) return st;
     E->ctl_valid = true;
     HIP_TRY(hipStreamSynchronize(s));
@@ -696,14 +1043,15 @@ pdf_status pdf_particles_import(pdf_ens E, int32_t problem, int64_t n, const dou
 
 pdf_status pdf_counters(pdf_ens E, int32_t problem, int64_t out[PDF_NCOUNTERS])
 {
-    if (!E || !out || problem != 0) {
+    if (!E || !out || problem < 0 || problem >= E->n_problems) {
         set_error("pdf_counters: invalid argument");
         return PDF_E_INVAL;
     }
     HIP_TRY(hipSetDevice(E->grid->device));
     HIP_TRY(hipStreamSynchronize(E->stream));
     std::vector<unsigned long long> c(NCOUNT * CNT_SLOTS);
-    HIP_TRY(hipMemcpy(c.data(), E->cnt, sizeof(unsigned long long) * c.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(c.data(), E->cnt + (size_t)problem * NCOUNT * CNT_SLOTS, sizeof(unsigned long long) * c.size(),
+                      hipMemcpyDeviceToHost));
     for (int q = 0; q < NCOUNT; ++q) {
         unsigned long long t = 0;
         for (int k = 0; k < CNT_SLOTS; ++k) t += c[(size_t)q * CNT_SLOTS + k];
@@ -732,6 +1080,96 @@ pdf_status pdf_timing(pdf_ens E, int32_t enable, double* ms_out, int64_t* launch
     }
     E->timing = enable != 0;
     return PDF_OK;
+}
+
+pdf_status pdf_get_options(pdf_ens E, pdf_options* out)
+{
+    if (!E || !out) {
+        set_error("pdf_get_options: null argument");
+        return PDF_E_INVAL;
+    }
+    out->use_graph = E->use_graph ? 1 : 0;
+    out->adv_block = E->adv_block;
+    out->ppl = E->ppl;
+    return PDF_OK;
+}
+
+pdf_status pdf_set_options(pdf_ens E, const pdf_options* opt)
+{
+    if (!E || !opt || (opt->adv_block != 64 && opt->adv_block != 128 && opt->adv_block != 256) ||
+        !(opt->ppl >= 1 && opt->ppl <= 8 && opt->ppl != 7)) {
+        set_error("pdf_set_options: adv_block must be 64, 128 or 256 and ppl one of 1..6, 8");
+        return PDF_E_INVAL;
+    }
+    HIP_TRY(hipSetDevice(E->grid->device));
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    if (opt->adv_block != E->adv_block || opt->ppl != E->ppl || (opt->use_graph != 0) != E->use_graph)
+        drop_graphs(E);
+    E->use_graph = opt->use_graph != 0;
+    E->adv_block = opt->adv_block;
+    E->ppl = opt->ppl;
+    return PDF_OK;
+}
+
+pdf_status pdf_autotune(pdf_ens E, const double* dt, int32_t steps_per_trial, void* hip_stream, pdf_options* chosen,
+                        int32_t* n_trials, double* trial_ms)
+{
+    if (!E || !dt || steps_per_trial < 1) {
+        set_error("pdf_autotune: invalid argument");
+        return PDF_E_INVAL;
+    }
+    HIP_TRY(hipSetDevice(E->grid->device));
+    hipStream_t s = as_stream(hip_stream);
+    pdf_options base{};
+    pdf_get_options(E, &base);
+    // candidates: particle-loop workgroup size x wavefront capacity of the element pass
+    std::vector<pdf_options> cand;
+    const int p0 = base.ppl;
+    const int ppls[3] = {p0 > 1 ? (p0 == 8 ? 6 : p0 - 1) : 1, p0, p0 >= 6 ? 8 : p0 + 1};
+    for (int b : {128, 256})
+        for (int q = 0; q < 3; ++q) {
+            if (q > 0 && ppls[q] == ppls[q - 1]) continue;
+            cand.push_back(pdf_options{base.use_graph, b, ppls[q]});
+        }
+    hipEvent_t t0, t1;
+    HIP_TRY(hipEventCreate(&t0));
+    HIP_TRY(hipEventCreate(&t1));
+    double best = 1e300;
+    pdf_options pick = base;
+    int k = 0;
+    for (const pdf_options& o : cand) {
+        pdf_status st = pdf_set_options(E, &o);
+        if (st == PDF_OK) st = pdf_step(E, dt, 1, hip_stream);   // warm-up, captures graphs
+        if (st != PDF_OK) {
+            (void)hipEventDestroy(t0);
+            (void)hipEventDestroy(t1);
+            return st;
+        }
+        (void)hipEventRecord(t0, s);
+        st = pdf_step(E, dt, steps_per_trial, hip_stream);
+        (void)hipEventRecord(t1, s);
+        if (st == PDF_OK && hipEventSynchronize(t1) != hipSuccess) st = PDF_E_HIP;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, t0, t1);
+        if (st != PDF_OK) {
+            (void)hipEventDestroy(t0);
+            (void)hipEventDestroy(t1);
+            return st;
+        }
+        if (trial_ms && n_trials && k < *n_trials) trial_ms[k] = ms;
+        ++k;
+        if (ms < best) {
+            best = ms;
+            pick = o;
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (n_trials) *n_trials = k;
+    pdf_status st = pdf_set_options(E, &pick);
+    if (st != PDF_OK) return st;
+    if (chosen) *chosen = pick;
+    return check_device_error(E);
 }
 
 }  // extern "C"

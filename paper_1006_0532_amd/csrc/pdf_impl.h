@@ -29,7 +29,7 @@ struct __attribute__((aligned(16))) ElemGeo {
     int32_t nbr[3];     // -1 across a boundary edge
     uint8_t kind[3];
     uint8_t wall;       // element touches a no-slip wall by an edge or a node
-    int32_t pad;
+    int32_t prob;       // problem of the ensemble the element belongs to
 };
 static_assert(sizeof(ElemGeo) % 16 == 0, "ElemGeo alignment");
 
@@ -53,11 +53,44 @@ struct ModelC {
     double nu, rho, C3, C4, CT, Cw1, Cw2, Cs, Ct;
 };
 
-// Structure-of-arrays particle state in HBM (FP64 form).
-struct Soa {
-    double *x, *y, *u0, *u1, *u2, *om, *psi, *w;
+// Structure-of-arrays particle state in HBM: positions always FP64, the rest in R
+// (double: FP64 form, float: mixed form).
+template <class R>
+struct SoaT {
+    double *x, *y;
+    R *u0, *u1, *u2, *om, *psi, *w;
     uint64_t* pid;
     int32_t* elem;  // host element; -1 = dead slot
+};
+
+// the same arrays untyped, as the host holds them
+struct SoaRaw {
+    double *x = nullptr, *y = nullptr;
+    void *u0 = nullptr, *u1 = nullptr, *u2 = nullptr, *om = nullptr, *psi = nullptr, *w = nullptr;
+    uint64_t* pid = nullptr;
+    int32_t* elem = nullptr;
+    template <class R>
+    SoaT<R> as() const
+    {
+        return SoaT<R>{x, y, (R*)u0, (R*)u1, (R*)u2, (R*)om, (R*)psi, (R*)w, pid, elem};
+    }
+};
+
+// Per-problem parameters of an ensemble (one entry per independent problem).
+struct ProbParams {
+    ModelC m;
+    double dt;                     // time step of the current pdf_step
+    double period;                 // x period of the problem's grid (0: none)
+    double src_x, src_y, src_r2;   // scalar source disk
+    double u_sigma, omega_shape;   // set-up distributions
+    RngKey key;                    // (seed lo, seed hi ^ problem)
+    int32_t src_cont;
+    int32_t bins0, bins1, bins2, minpb;
+    int32_t ppe;
+    int64_t eoff, ne;              // element range in the ensemble
+    int64_t noff, nn;              // node range
+    int64_t soff;                  // first set-up slot
+    uint64_t next_pid;             // next particle id of the problem
 };
 
 }  // namespace pdfgpu
@@ -79,28 +112,47 @@ struct pdf_grid_s {
     int32_t* d_n2e = nullptr;
 };
 
+// Device view of the grid an ensemble runs on: the grid's own arrays for one problem,
+// concatenated copies (element, node and CSR indices offset) for several.
+struct DevGrid {
+    int64_t nn = 0, ne = 0;
+    pdfgpu::ElemGeo* geo = nullptr;
+    double* node = nullptr;          // FP64 node records
+    float* node32 = nullptr;         // FP32 node records (mixed form)
+    int64_t* n2e_ptr = nullptr;
+    int32_t* n2e = nullptr;
+    bool owned = false;              // arrays allocated by the ensemble
+};
+
 struct pdf_ens_s {
-    pdf_grid grid = nullptr;
+    pdf_grid grid = nullptr;         // grid of problem 0
+    std::vector<pdf_grid> grids;     // grid of every problem
+    std::vector<pdf_init_desc> descs;
+    std::vector<pdfgpu::ProbParams> h_prm;
+    pdfgpu::ProbParams* d_prm = nullptr;
+    int32_t n_problems = 1;
+    int32_t precision = 0;           // PDF_FP64 or PDF_MIXED
+    DevGrid dg;
     pdf_init_desc d{};
-    int32_t problem = 0;
     hipStream_t stream = nullptr;
     int64_t cap = 0;
     int64_t n_slots_ub = 0;   // host-side upper bound of the used slots
     int64_t step = 0;
     uint64_t next_pid = 0;
     int cur = 0;              // which SoA buffer is current
-    pdfgpu::Soa buf[2]{};
+    pdfgpu::SoaRaw buf[2]{};
     int32_t* counts = nullptr;   // [ne] particles per element (zero between steps)
     int32_t* start = nullptr;    // [ne+1] segment starts of the current buffer
     int32_t* idx = nullptr;      // [cap] slot of each grouped particle
     int32_t* scan_tmp = nullptr; // block sums
-    int64_t* d_meta = nullptr;   // [0] used slots, [1] report scratch...
-    double* part = nullptr;      // [ne][3][NPART] per-vertex partial sums
+    int64_t* d_meta = nullptr;   // [0] used slots, [1] live, [2] clones of the last control, [4] step
+    void* part = nullptr;        // [ne][3][NPART] per-vertex partial sums (state precision)
     double* stats = nullptr;     // [nn][NSTAT]
-    double* shift = nullptr;     // [nn][5] reference values of the single-pass moments
+    void* shift = nullptr;       // [nn][5] reference values of the single-pass moments (state precision)
     double* tm = nullptr;        // [ne] micromixing timescale, Eq. (25)
     uint32_t* err = nullptr;     // sticky device error word
-    unsigned long long* cnt = nullptr;  // [NCOUNT][CNT_SLOTS]
+    unsigned long long* cnt = nullptr;  // [n_problems][NCOUNT][CNT_SLOTS]
+    unsigned long long* d_scalar = nullptr;  // small reduction results
     // element-pass scratch for elements too large for on-chip memory, [cap] each
     double* gkey = nullptr;      // 2 doubles per particle (key, pid bits)
     int32_t* gord = nullptr;     // 2 ints per particle
@@ -116,6 +168,15 @@ struct pdf_ens_s {
     int64_t t_n[pdfgpu::T_N] = {0};
     int lds_max = 0;            // particles per element on chip in the workgroup kernel
     int ppl = 4;                // particles per lane in the wavefront kernel
+    int adv_block = 256;        // threads per workgroup of the particle loop
+    // graph-captured steps
+    bool use_graph = false;
+    bool capturing = false;    // a step is being captured into a graph
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // two steps starting from buffer 0 / 1
+    int64_t g_nub[2] = {-1, -1};
+    std::vector<double> g_dt[2];
     int32_t* big_list = nullptr;
     int32_t* big_count = nullptr;
     bool ctl_valid = false;     // the current buffer holds the canonical order of a pass

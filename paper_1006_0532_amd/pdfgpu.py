@@ -27,7 +27,9 @@ STATUS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "HIP", -4: "MESH", -5: "CAPACIT
 # every symbol include/pdf.h declares
 EXPORTS = ["pdf_grid_create", "pdf_grid_destroy", "pdf_particles_init", "pdf_ens_destroy", "pdf_step",
            "pdf_stats", "pdf_control", "pdf_count", "pdf_particles_export", "pdf_particles_import",
-           "pdf_counters", "pdf_timing", "pdf_sync", "pdf_last_error"]
+           "pdf_counters", "pdf_timing", "pdf_get_options", "pdf_set_options", "pdf_autotune", "pdf_sync",
+           "pdf_last_error"]
+PDF_FP64, PDF_MIXED = 0, 1
 
 
 class PdfError(RuntimeError):
@@ -55,6 +57,10 @@ class InitDesc(C.Structure):
                 ("src_x", C.c_double), ("src_y", C.c_double), ("src_r", C.c_double),
                 ("src_continuous", C.c_int32), ("bins", C.c_int32 * 3), ("min_per_bin", C.c_int32),
                 ("precision", C.c_int32), ("seed", C.c_uint64), ("capacity", C.c_int64)]
+
+
+class Options(C.Structure):
+    _fields_ = [("use_graph", C.c_int32), ("adv_block", C.c_int32), ("ppl", C.c_int32)]
 
 
 class ControlReport(C.Structure):
@@ -88,6 +94,9 @@ def load(path: str = LIB_PATH):
                                  C.c_uint64, vp],
         "pdf_counters": [vp, C.c_int32, i64p],
         "pdf_timing": [vp, C.c_int32, dp, i64p],
+        "pdf_get_options": [vp, C.POINTER(Options)],
+        "pdf_set_options": [vp, C.POINTER(Options)],
+        "pdf_autotune": [vp, dp, C.c_int32, vp, C.POINTER(Options), ip, dp],
         "pdf_sync": [vp],
     }
     for name, args in sig.items():
@@ -162,48 +171,71 @@ def make_init(d: dict, capacity: int = 0, precision: int = 0) -> InitDesc:
 
 
 class Ensemble:
-    def __init__(self, grid: Grid, init: dict, capacity: int = 0, stream: int | None = None):
+    """Particles of one problem, or of several independent problems advanced together
+    (grid and init may be lists of equal length; problem p is numbered p)."""
+
+    def __init__(self, grid, init, capacity: int = 0, precision: int = PDF_FP64, stream: int | None = None):
         L = load()
-        self.grid = grid
-        self.desc = make_init(init, capacity)
-        grids = (C.c_void_p * 1)(grid.h.value)
+        grids = list(grid) if isinstance(grid, (list, tuple)) else [grid]
+        inits = list(init) if isinstance(init, (list, tuple)) else [init]
+        if len(grids) != len(inits):
+            raise ValueError("one init descriptor per grid")
+        self.grids = grids
+        self.grid = grids[0]
+        self.n_problems = len(grids)
+        self.precision = int(precision)
+        if isinstance(capacity, (list, tuple)):
+            caps = list(capacity)
+        elif self.n_problems == 1 or not capacity:
+            caps = [capacity] + [0] * (self.n_problems - 1)
+        else:
+            raise ValueError("several problems take one capacity per problem")
+        descs = (InitDesc * self.n_problems)(*[make_init(d, c, precision) for d, c in zip(inits, caps)])
+        self.desc = descs[0]
+        self._descs = descs
+        hs = (C.c_void_p * self.n_problems)(*[g.h.value for g in grids])
         h = C.c_void_p()
         self.stream = current_stream() if stream is None else stream
-        _check(L.pdf_particles_init(grids, C.byref(self.desc), 1, C.c_void_p(self.stream), C.byref(h)))
+        _check(L.pdf_particles_init(hs, descs, self.n_problems, C.c_void_p(self.stream), C.byref(h)))
         self.h = h
 
-    def step(self, dt: float, n: int = 1):
-        d = (C.c_double * 1)(float(dt))
-        _check(load().pdf_step(self.h, d, int(n), C.c_void_p(self.stream)))
+    def _dts(self, dt):
+        v = list(dt) if isinstance(dt, (list, tuple, np.ndarray)) else [dt] * self.n_problems
+        if len(v) != self.n_problems:
+            raise ValueError("one time step per problem")
+        return (C.c_double * self.n_problems)(*[float(x) for x in v])
+
+    def step(self, dt, n: int = 1):
+        _check(load().pdf_step(self.h, self._dts(dt), int(n), C.c_void_p(self.stream)))
 
     def sync(self):
         _check(load().pdf_sync(self.h))
 
-    def stats(self) -> np.ndarray:
-        out = np.empty((self.grid.nn, PDF_NSTAT))
-        _check(load().pdf_stats(self.h, 0, out.ctypes.data_as(C.c_void_p), 0, C.c_void_p(self.stream)))
+    def stats(self, problem: int = 0) -> np.ndarray:
+        out = np.empty((self.grids[problem].nn, PDF_NSTAT))
+        _check(load().pdf_stats(self.h, int(problem), out.ctypes.data_as(C.c_void_p), 0, C.c_void_p(self.stream)))
         return out
 
-    def stats_device(self, ptr: int):
-        _check(load().pdf_stats(self.h, 0, C.c_void_p(ptr), 1, C.c_void_p(self.stream)))
+    def stats_device(self, ptr: int, problem: int = 0):
+        _check(load().pdf_stats(self.h, int(problem), C.c_void_p(ptr), 1, C.c_void_p(self.stream)))
 
     def control(self, n_min: int, n_max: int) -> dict:
         r = ControlReport()
         _check(load().pdf_control(self.h, int(n_min), int(n_max), C.byref(r), C.c_void_p(self.stream)))
         return {n: getattr(r, n) for n, _ in ControlReport._fields_}
 
-    def count(self) -> int:
+    def count(self, problem: int = -1) -> int:
         v = C.c_int64()
-        _check(load().pdf_count(self.h, 0, C.byref(v)))
+        _check(load().pdf_count(self.h, int(problem), C.byref(v)))
         return int(v.value)
 
-    def export(self, sort_by_pid: bool = True) -> dict:
-        n = self.count()
+    def export(self, sort_by_pid: bool = True, problem: int = 0) -> dict:
+        n = self.count(problem)
         o = dict(x=np.empty(n), y=np.empty(n), u=np.empty((n, 3)), om=np.empty(n), psi=np.empty(n),
                  w=np.empty(n), pid=np.empty(n, np.uint64), elem=np.empty(n, np.int32))
         got = C.c_int64()
-        _check(load().pdf_particles_export(self.h, 0, n, *[_ptr(o[k], C.c_double) for k in
-                                                           ("x", "y", "u", "om", "psi", "w")],
+        _check(load().pdf_particles_export(self.h, int(problem), n, *[_ptr(o[k], C.c_double) for k in
+                                                                      ("x", "y", "u", "om", "psi", "w")],
                                            _ptr(o["pid"], C.c_uint64), _ptr(o["elem"], C.c_int32),
                                            C.byref(got), C.c_void_p(self.stream)))
         assert got.value == n
@@ -221,9 +253,9 @@ class Ensemble:
                                            _ptr(pid, C.c_uint64), _ptr(el, C.c_int32), int(step),
                                            int(next_pid), C.c_void_p(self.stream)))
 
-    def counters(self) -> dict:
+    def counters(self, problem: int = 0) -> dict:
         o = (C.c_int64 * PDF_NCOUNTERS)()
-        _check(load().pdf_counters(self.h, 0, o))
+        _check(load().pdf_counters(self.h, int(problem), o))
         return dict(zip(COUNTER_NAMES, o[:]))
 
     def timing(self, enable: bool):
@@ -231,6 +263,27 @@ class Ensemble:
         cnt = (C.c_int64 * PDF_NTIMERS)()
         _check(load().pdf_timing(self.h, int(enable), ms, cnt))
         return {TIMER_NAMES[i]: (ms[i], cnt[i]) for i in range(PDF_NTIMERS)}
+
+    def options(self) -> dict:
+        o = Options()
+        _check(load().pdf_get_options(self.h, C.byref(o)))
+        return {n: getattr(o, n) for n, _ in Options._fields_}
+
+    def set_options(self, **kw):
+        cur = self.options()
+        cur.update(kw)
+        o = Options(**{n: int(cur[n]) for n, _ in Options._fields_})
+        _check(load().pdf_set_options(self.h, C.byref(o)))
+
+    def autotune(self, dt, steps_per_trial: int = 2):
+        """Times the candidate launch options on the live ensemble (which advances) and
+        keeps the fastest; returns (chosen options, [trial ms])."""
+        o = Options()
+        n = C.c_int32(16)
+        ms = (C.c_double * 16)()
+        _check(load().pdf_autotune(self.h, self._dts(dt), int(steps_per_trial), C.c_void_p(self.stream),
+                                   C.byref(o), C.byref(n), ms))
+        return {k: getattr(o, k) for k, _ in Options._fields_}, list(ms[:n.value])
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:

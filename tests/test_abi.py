@@ -43,3 +43,13 @@ def test_host_side_argument_errors():
     assert L.pdf_step(None, None, 1, None) == -1
     assert L.pdf_control(None, 5, 1, None, None) == -1
     assert L.pdf_sync(None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(pdfgpu.LIB_PATH), reason="libpdfgpu.so not built")
+def test_option_and_tuning_argument_errors():
+    L = pdfgpu.load()
+    o = pdfgpu.Options(0, 256, 4)
+    assert L.pdf_set_options(None, ctypes.byref(o)) == -1
+    assert L.pdf_get_options(None, ctypes.byref(o)) == -1
+    assert L.pdf_autotune(None, None, 1, None, None, None, None) == -1
+    assert L.pdf_particles_init(None, None, 0, None, None) == -1

@@ -1,0 +1,252 @@
+"""GPU tests of the two forms beyond the plain FP64 step, through the C ABI:
+
+* mixed precision (FP32 velocity / frequency / scalar / weight, FP64 positions and
+  tracking): nodal statistics against the FP64 oracle, per statistic, as the
+  W-weighted relative L2 error ||s - s_ref||_{2,W} / ||s_ref||_{2,W};
+* several problems in one ensemble: every problem against the oracle run alone (same
+  key: seed high word XOR problem index) and bitwise against a single-problem GPU
+  ensemble; HIP-graph replay and the autotuner, which must not change any result.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1006_0532_amd import workloads as W
+from tests.common import box
+from tests.parity import compare_states, compare_stats
+
+pytestmark = pytest.mark.gpu
+
+MEAN_BOUND = 1e-5      # W, <U_i>, <omega>
+SECOND_BOUND = 1e-4    # second moments and the scalar mean / variance
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "a GPU is required"
+    from paper_1006_0532_amd import pdfgpu
+    pdfgpu.load()
+    return pdfgpu
+
+
+def _length(mesh):
+    return mesh.period_x if mesh.period_x > 0 else float(np.ptp(mesh.xy[:, 0]))
+
+
+def weighted_rel_l2(s, ref):
+    """Per-statistic ||s - ref||_{2,W} / ||ref||_{2,W}, W = the reference nodal weight."""
+    ok = ~np.isnan(ref).any(axis=1) & ~np.isnan(s).any(axis=1)
+    W = ref[ok, 0]
+    out = []
+    for q in range(ref.shape[1]):
+        num = np.sqrt(np.sum(W * (s[ok, q] - ref[ok, q]) ** 2))
+        den = np.sqrt(np.sum(W * ref[ok, q] ** 2))
+        out.append(num / den if den > 0 else num)
+    return np.array(out), int((~ok).sum())
+
+
+def _check_mixed_stats(sg, so, label):
+    err, nan_nodes = weighted_rel_l2(sg, so)
+    _say(f"  {label}: W-weighted relative L2 per statistic: {np.array2string(err, precision=2)}")
+    assert nan_nodes == int(np.isnan(so).any(axis=1).sum())
+    assert err[0] <= MEAN_BOUND
+    assert np.all(err[1:5] <= MEAN_BOUND), err[1:5]
+    assert err[5] <= SECOND_BOUND
+    assert np.all(err[6:] <= SECOND_BOUND), err[6:]
+    return err
+
+
+def test_mixed_channel_small_statistics(gpu):
+    """Mixed form on the small channel (20 steps of 1e-3): statistics within the bounds of
+    the FP64 oracle's; particles keep their ids and stay within FP32 rounding of the FP64
+    trajectories."""
+    _say("test_mixed_channel_small_statistics")
+    mesh, f, mo, ini = W.channel_small()
+    og = O.Grid(mesh, f, mo)
+    oe = O.Ensemble(og, ini)
+    gg = gpu.Grid(mesh, f, mo)
+    ge = gpu.Ensemble(gg, ini, precision=gpu.PDF_MIXED)
+    _check_mixed_stats(ge.stats(), oe.stats(), "set-up")
+    for n in range(20):
+        oe.step(1e-3)
+        ge.step(1e-3)
+    err = _check_mixed_stats(ge.stats(), oe.stats(), "step 20")
+    g, r = ge.export(), oe.export()
+    assert np.array_equal(g["pid"], r["pid"])
+    dx = np.abs(g["x"] - r["x"])
+    dx = np.minimum(dx, np.abs(dx - mesh.period_x))
+    du = np.abs(g["u"] - r["u"]).max(axis=1)
+    _say(f"  max |dx| {dx.max():.2e}, 99.9% |du| {np.quantile(du, 0.999):.2e}")
+    assert np.quantile(dx, 0.999) < 1e-7 and np.quantile(du, 0.999) < 1e-5
+    assert (g["elem"] != r["elem"]).mean() < 1e-4
+    cg, co = ge.counters(), oe.counters()
+    for k in cg:
+        assert abs(cg[k] - co[k]) <= max(2, 1e-3 * co[k]), (k, cg[k], co[k])
+
+
+def test_mixed_cavity_with_control(gpu):
+    """Mixed form on the street canyon with number control every other step."""
+    _say("test_mixed_cavity_with_control")
+    mesh, f, mo, ini = W.cavity_small()
+    og = O.Grid(mesh, f, mo)
+    oe = O.Ensemble(og, ini)
+    gg = gpu.Grid(mesh, f, mo)
+    ge = gpu.Ensemble(gg, ini, precision=gpu.PDF_MIXED)
+    for n in range(10):
+        oe.step(1e-3)
+        ge.step(1e-3)
+        if n % 2 == 1:
+            ro, rg = oe.control(40, 60), ge.control(40, 60)
+            # decisions depend on counts only; counts can differ by an edge-crossing
+            assert abs(ro["live"] - rg["live"]) <= 2 and abs(ro["cloned"] - rg["cloned"]) <= 2
+    _check_mixed_stats(ge.stats(), oe.stats(), "step 10")
+
+
+def test_mixed_conservation_of_control(gpu):
+    """Number control in FP32 conserves the total weight and weighted sums of every
+    element (to FP32 rounding) and gives fresh unique ids."""
+    _say("test_mixed_conservation_of_control")
+    mesh = W.channel_mesh(10, 12, seed=3)
+    f = W.channel_fields(mesh)
+    ini = W.init_desc(ppe=40, bins=(4, 2, 2), src_x=3.0, src_r=0.5)
+    gg = gpu.Grid(mesh, f, W.model_constants())
+    ge = gpu.Ensemble(gg, ini, precision=gpu.PDF_MIXED)
+    ge.step(2e-3)
+    a = ge.export(sort_by_pid=False)
+    rep = ge.control(38, 42)
+    b = ge.export(sort_by_pid=False)
+    assert rep["cloned"] > 0 and rep["merged"] > 0
+    assert len(np.unique(b["pid"])) == len(b["pid"])
+    ne = mesh.n_elems
+    def sums(s, q):
+        v = s["w"] if q == "w" else s["w"] * (s[q] if q != "u" else s["u"][:, 0])
+        return np.bincount(s["elem"], weights=v, minlength=ne)
+    for q in ("w", "psi", "om", "u"):
+        sa, sb = sums(a, q), sums(b, q)
+        assert np.allclose(sa, sb, rtol=2e-6, atol=1e-6), q
+
+
+def _problems():
+    """Three uneven problems: a channel, a street canyon and a jittered box with large
+    steps, each with its own model constants, bins, seed and time step."""
+    m0 = W.channel_mesh(12, 10, seed=7)
+    p0 = (m0, W.channel_fields(m0), W.model_constants(),
+          W.init_desc(ppe=40, bins=(4, 2, 2), src_x=2.0, src_r=0.3, seed=101), 1e-3)
+    m1 = W.cavity_mesh(8, 6, 6, seed=9)
+    p1 = (m1, W.cavity_fields(m1), W.model_constants(nu=2e-4),
+          W.init_desc(ppe=60, bins=(3, 2, 2), src_x=1.5, src_y=0.5, src_r=0.2, seed=202), 5e-4)
+    m2 = box(5, 4, length=2.5, jitter=0.2, seed=5)
+    p2 = (m2, W.uniform_fields(m2, mean_u=(1.0, 0.5, 0.0), mean_omega=3.0), W.model_constants(nu=1e-3),
+          W.init_desc(ppe=200, u_sigma=0.4, src_x=1.0, src_r=0.3, bins=(3, 2, 1), seed=303), 0.02)
+    return [p0, p1, p2]
+
+
+def _oracle_for(problem_index, mesh, f, mo, ini):
+    """The oracle keys a lone problem as problem 0: the same key needs seed ^ (p << 32)."""
+    d = dict(ini)
+    d["seed"] = int(ini["seed"]) ^ (problem_index << 32)
+    og = O.Grid(mesh, f, mo)
+    return og, O.Ensemble(og, d)
+
+
+def test_batched_problems_match_the_oracle(gpu):
+    _say("test_batched_problems_match_the_oracle")
+    probs = _problems()
+    grids = [gpu.Grid(m, f, mo) for m, f, mo, ini, dt in probs]
+    ge = gpu.Ensemble(grids, [ini for m, f, mo, ini, dt in probs])
+    orc = [_oracle_for(p, m, f, mo, ini) for p, (m, f, mo, ini, dt) in enumerate(probs)]
+    dts = [dt for *_, dt in probs]
+    for n in range(5):
+        ge.step(dts)
+        for (og, oe), dt in zip(orc, dts):
+            oe.step(dt)
+        if n == 2:
+            rg = ge.control(40, 70)
+            ro = [oe.control(40, 70) for og, oe in orc]
+            for k in rg:
+                assert rg[k] == sum(r[k] for r in ro), (k, rg, ro)
+    assert ge.count() == sum(oe.count() for og, oe in orc)
+    for p, ((m, f, mo, ini, dt), (og, oe)) in enumerate(zip(probs, orc)):
+        assert ge.count(p) == oe.count()
+        frame = og.export()["frame"]
+        rep, excl = compare_states(ge.export(problem=p), oe.export(), frame, _length(m))
+        skip = set(m.tri[list(excl)].ravel().tolist()) if excl else set()
+        compare_stats(ge.stats(p), oe.stats(), skip)
+        assert ge.counters(p) == oe.counters(), p
+        _say(f"  problem {p}: {rep}")
+
+
+def test_batched_equals_single_problem_ensembles(gpu):
+    """Problem p of a batch is bitwise the single-problem ensemble with seed ^ (p << 32)."""
+    _say("test_batched_equals_single_problem_ensembles")
+    probs = _problems()
+    grids = [gpu.Grid(m, f, mo) for m, f, mo, ini, dt in probs]
+    ge = gpu.Ensemble(grids, [ini for m, f, mo, ini, dt in probs])
+    singles = []
+    for p, (m, f, mo, ini, dt) in enumerate(probs):
+        d = dict(ini)
+        d["seed"] = int(ini["seed"]) ^ (p << 32)
+        singles.append(gpu.Ensemble(grids[p], d))
+    dts = [dt for *_, dt in probs]
+    for n in range(4):
+        ge.step(dts)
+        for e, dt in zip(singles, dts):
+            e.step(dt)
+    for p, e in enumerate(singles):
+        a, b = ge.export(problem=p), e.export()
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (p, k)
+        assert np.array_equal(ge.stats(p), e.stats(), equal_nan=True)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_is_bitwise_eager(gpu, precision):
+    """Steps replayed from captured HIP graphs equal eager steps after every chunk, with
+    eager work (control, export) between replays and a time-step change."""
+    _say(f"test_graph_replay_is_bitwise_eager precision={precision}")
+    probs = _problems()
+    grids = [gpu.Grid(m, f, mo) for m, f, mo, ini, dt in probs]
+    inits = [ini for m, f, mo, ini, dt in probs]
+    a = gpu.Ensemble(grids, inits, precision=precision)
+    b = gpu.Ensemble(grids, inits, precision=precision)
+    b.set_options(use_graph=1)
+    dts = [dt for *_, dt in probs]
+    for chunk, ctl in ((2, False), (3, True), (4, False), (1, False), (6, True)):
+        if chunk == 4:
+            dts = [0.5 * d for d in dts]
+        a.step(dts, chunk)
+        b.step(dts, chunk)
+        if ctl:
+            assert a.control(40, 70) == b.control(40, 70)
+        for p in range(len(probs)):
+            ea, eb = a.export(problem=p), b.export(problem=p)
+            for k in ea:
+                assert np.array_equal(ea[k], eb[k]), (chunk, p, k)
+            assert np.array_equal(a.stats(p), b.stats(p), equal_nan=True)
+    for p in range(len(probs)):
+        assert a.counters(p) == b.counters(p)
+
+
+def test_autotune_changes_no_result(gpu):
+    _say("test_autotune_changes_no_result")
+    mesh, f, mo, ini = W.channel_small(nx=20, ny=24)
+    gg = gpu.Grid(mesh, f, mo)
+    a = gpu.Ensemble(gg, ini)
+    b = gpu.Ensemble(gg, ini)
+    chosen, ms = a.autotune(1e-3, steps_per_trial=2)
+    _say(f"  chosen {chosen}, trials {np.round(ms, 3).tolist()}")
+    steps = len(ms) * 3
+    b.step(1e-3, steps)
+    sa, sb = a.export(), b.export()
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    np.testing.assert_allclose(a.stats(), b.stats(), rtol=1e-12, atol=1e-15)
+    assert a.options()["adv_block"] in (128, 256)
