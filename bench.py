@@ -4,8 +4,10 @@ Workload: FP64 periodic channel, 400 x 500 quads -> 400 000 triangles, 200 parti
 element (8e7 particles), dt = 2e-4; one timed step = pdf_step (advance, track, group,
 bin, mix, statistics) + pdf_control(150, 250) (number control), inputs resident in HBM.
 Prints one JSON line with whole-job throughput, the roofline of the dominant kernel
-(timed with HIP events on the ensemble's stream) and the CPU oracle timed on a bounded
-sample of the same workload.
+(timed with HIP events on the ensemble's stream), the CPU oracle timed on a bounded
+sample of the same workload, and the two other forms: the same workload in mixed
+precision, and 64 uneven independent problems advanced as one batched ensemble against
+the same problems advanced one at a time.
 """
 from __future__ import annotations
 
@@ -66,6 +68,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--copy-calib", action="store_true",
                    help="run one 1 GiB device copy first (known-size kernel for HBM counter scaling)")
+    p.add_argument("--no-forms", action="store_true",
+                   help="skip the mixed-precision and batched measurements")
+    p.add_argument("--form-steps", type=int, default=10)
+    p.add_argument("--batched-problems", type=int, default=64)
     return p.parse_args()
 
 
@@ -97,6 +103,123 @@ def cpu_baseline(args, dt, ctl):
             "sample": f"channel generator at {nx}x{ny} quads ({2 * nx * ny} triangles), "
                       f"{args.ppe} particles/element, {done} steps of dt={dt} with control "
                       f"{list(ctl)}, {el:.1f} s"}
+
+
+STAT_FIELDS = {"W": ([0], [1.0]), "U": ([1, 2, 3], [1.0] * 3), "omega": ([4], [1.0]), "psi": ([5], [1.0]),
+               "R": ([6, 7, 8, 9, 10, 11], [1.0, 1.0, 1.0, 2.0, 2.0, 2.0]), "psi_var": ([12], [1.0])}
+
+
+def field_errors(s, ref):
+    """W-weighted relative L2 error ||s - ref||_{2,W} / ||ref||_{2,W} of every nodal field
+    (mean velocity as a vector, Reynolds stresses as a tensor in the Frobenius norm)."""
+    import numpy as np
+    ok = ~np.isnan(ref).any(axis=1) & ~np.isnan(s).any(axis=1)
+    W = ref[ok, 0]
+    out = {}
+    for name, (cols, wts) in STAT_FIELDS.items():
+        d = sum(c * (s[ok, q] - ref[ok, q]) ** 2 for q, c in zip(cols, wts))
+        r = sum(c * ref[ok, q] ** 2 for q, c in zip(cols, wts))
+        num, den = float(np.sqrt(np.sum(W * d))), float(np.sqrt(np.sum(W * r)))
+        out[name] = num / den if den > 0 else num
+    return out
+
+
+def timed_steps(ens, dt, steps, ctl=None):
+    """Live particle-steps and wall time of `steps` steps (each followed by control when
+    ctl is given), bracketed by device synchronisation."""
+    import torch
+    ens.sync()
+    torch.cuda.synchronize()
+    n_fixed = None if ctl else ens.count()     # without control the live count is constant
+    live, t0 = 0, time.perf_counter()
+    if ctl:
+        for _ in range(steps):
+            live += ens.count()
+            ens.step(dt)
+            ens.control(*ctl)
+    else:
+        ens.step(dt, steps)
+        live = n_fixed * steps
+    ens.sync()
+    torch.cuda.synchronize()
+    return live, time.perf_counter() - t0
+
+
+def mixed_form(args, mesh, f, mo, ini, dt, ctl):
+    """The same workload (step + control) in the mixed form."""
+    from paper_1006_0532_amd import pdfgpu
+    n0 = mesh.n_elems * args.ppe
+    grid = pdfgpu.Grid(mesh, f, mo)
+    ens = pdfgpu.Ensemble(grid, ini, capacity=int(1.3 * n0) + 1024, precision=pdfgpu.PDF_MIXED)
+    for _ in range(args.warmup):
+        ens.step(dt)
+        ens.control(*ctl)
+    ens.timing(True)
+    live, el = timed_steps(ens, dt, args.form_steps, ctl)
+    tim = ens.timing(False)
+    out = {"value": live / el, "ms_per_step": 1e3 * el / args.form_steps, "steps": args.form_steps,
+           "per_kernel_ms": {k: round(v[0] / v[1], 4) for k, v in tim.items() if v[1] > 0}}
+    ens.close()
+    grid.close()
+    return out
+
+
+def mixed_error(mesh, f, mo, ini, dt, steps):
+    """Nodal statistics of the mixed form against the FP64 form on the full workload after
+    `steps` steps without number control (control decisions on counts that differ by one
+    edge-crossing particle would start different random streams): W-weighted relative L2
+    per field."""
+    from paper_1006_0532_amd import pdfgpu
+    grid = pdfgpu.Grid(mesh, f, mo)
+    st = {}
+    for prec in (pdfgpu.PDF_FP64, pdfgpu.PDF_MIXED):
+        ens = pdfgpu.Ensemble(grid, ini, precision=prec)
+        ens.step(dt, steps)
+        st[prec] = ens.stats()
+        ens.close()
+    grid.close()
+    err = field_errors(st[pdfgpu.PDF_MIXED], st[pdfgpu.PDF_FP64])
+    err["steps"] = steps
+    return err
+
+
+def batched_form(args):
+    """64 independent channel / street-canyon problems of uneven size (triangles
+    log-uniform in [1e3, 2e5], 20-400 particles per element): advanced together (one
+    launch per kernel, graph-replayed steps, autotuned launch options) in FP64 and in the
+    mixed form, against the same problems advanced one ensemble at a time (FP64)."""
+    from paper_1006_0532_amd import pdfgpu, workloads as W
+    probs = W.batched_problems(args.batched_problems)
+    dts = [p[4] for p in probs]
+    grids = [pdfgpu.Grid(m, f, mo) for m, f, mo, ini, dt in probs]
+    inits = [ini for m, f, mo, ini, dt in probs]
+    caps = [int(1.05 * m.n_elems * ini["ppe"]) + 1024 for m, f, mo, ini, dt in probs]
+    n_total = sum(m.n_elems * ini["ppe"] for m, f, mo, ini, dt in probs)
+    out = {"problems": len(probs), "triangles": int(sum(m.n_elems for m, *_ in probs)), "particles": int(n_total),
+           "steps": args.form_steps}
+    for name, prec in (("fp64", pdfgpu.PDF_FP64), ("mixed", pdfgpu.PDF_MIXED)):
+        ens = pdfgpu.Ensemble(grids, inits, capacity=caps, precision=prec)
+        ens.set_options(use_graph=1)
+        chosen, trials = ens.autotune(dts, steps_per_trial=2)
+        live, el = timed_steps(ens, dts, args.form_steps)
+        out[name] = {"value": live / el, "ms_per_step": 1e3 * el / args.form_steps, "options": chosen,
+                     "autotune_trial_ms": [round(t, 3) for t in trials]}
+        ens.close()
+    # the same FP64 problems one ensemble at a time (seed ^ p << 32 gives the same streams)
+    live_tot, el_tot = 0, 0.0
+    for p, (g, ini, dt, cap) in enumerate(zip(grids, inits, dts, caps)):
+        d = dict(ini)
+        d["seed"] = int(ini["seed"]) ^ (p << 32)
+        e = pdfgpu.Ensemble(g, d, capacity=cap)
+        e.step(dt)
+        live, el = timed_steps(e, dt, args.form_steps)
+        live_tot += live
+        el_tot += el
+        e.close()
+    out["plain_fp64_one_at_a_time"] = {"value": live_tot / el_tot, "ms_per_step": 1e3 * el_tot / args.form_steps}
+    for g in grids:
+        g.close()
+    return out
 
 
 def main():
@@ -173,6 +296,20 @@ def main():
             per_kernel[k]["GB/s"] = round(bpp * mean_live / (avg * 1e-3) / 1e9, 1)
     print(f"[bench] per kernel: {json.dumps(per_kernel)}", file=sys.stderr, flush=True)
 
+    forms = None
+    if not args.no_forms:
+        forms = {"fp64": {"value": value, "ms_per_step": 1e3 * elapsed / args.steps}}
+        ens.close()
+        grid.close()
+        forms["mixed"] = mixed_form(args, mesh, f, mo, ini, dt, ctl)
+        forms["mixed"]["speedup_vs_fp64"] = forms["mixed"]["value"] / value
+        forms["mixed"]["stat_error_vs_fp64"] = mixed_error(mesh, f, mo, ini, dt, args.form_steps)
+        print(f"[bench] mixed: {json.dumps(forms['mixed'])}", file=sys.stderr, flush=True)
+        forms["batched"] = batched_form(args)
+        b = forms["batched"]
+        b["speedup_vs_plain"] = b["fp64"]["value"] / b["plain_fp64_one_at_a_time"]["value"]
+        print(f"[bench] batched: {json.dumps(b)}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, dt, ctl)
@@ -185,7 +322,7 @@ def main():
         "config": {"workload": "channel_large", "triangles": mesh.n_elems, "nodes": mesh.n_nodes,
                    "particles": n0, "ppe": args.ppe, "dt": dt, "control": list(ctl),
                    "bins": [4, 2, 2], "precision": "fp64", "parallelism": "single GPU"},
-        "roofline": roof, "per_kernel": per_kernel, "cpu_baseline": cpu,
+        "roofline": roof, "per_kernel": per_kernel, "cpu_baseline": cpu, "forms": forms,
     }
     print(json.dumps(out), flush=True)
 

@@ -47,7 +47,6 @@ struct ElementArgs {
     int64_t ne;
     int64_t cap;
     int32_t lds_max;
-    int32_t ppl;          // particles per lane of the wavefront kernel (1..6, 8)
     int32_t* big_list;    // [ne] elements left to the workgroup kernel
     int32_t* big_count;
     double* gkey;
@@ -98,8 +97,9 @@ struct ControlArgs {
 
 template <class R>
 void launch_advance(const AdvanceArgs<R>& a, int64_t n_ub, bool batched, int block, hipStream_t s);
+// wavefront tiers of increasing capacity 64 x tiers[t], then the workgroup kernel
 template <class R>
-void launch_element_pass(const ElementArgs<R>& a, hipStream_t s);
+void launch_element_pass(const ElementArgs<R>& a, const int* tiers, int n_tiers, hipStream_t s);
 template <class R>
 hipError_t prepare_element_pass(int lds_max);
 template <class R>

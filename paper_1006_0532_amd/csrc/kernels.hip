@@ -713,8 +713,9 @@ __global__ void __launch_bounds__(NT) k_element_block(ElementArgs<R> a)
     R* bmean = reinterpret_cast<R*>(smem + (NT / 64) * 3 * NPART * sizeof(double));   // [MAXBINS]
     unsigned char* p = smem + (NT / 64) * 3 * NPART * sizeof(double) + MAXBINS * sizeof(double);
     const int nbig = *a.big_count;
+    const int32_t* big = a.big_list;
     for (int k = blockIdx.x; k < nbig; k += gridDim.x) {
-        const int32_t e = a.big_list[k];
+        const int32_t e = big[k];
         const int64_t s0 = a.start[e];
         const int n = a.start[e + 1] - a.start[e];
         if (n <= a.lds_max) {
@@ -760,8 +761,11 @@ struct WaveBlock {
 // in load order while the three sort levels rank (U_l, pid) keys staged in LDS; then each
 // lane takes the particles at canonical positions lane + 64 r, so bin sums, partial sums
 // and the coalesced write-out follow the canonical order only.
+// Tiers of increasing capacity: a launch takes the elements with n_below < n <= 64 PPL
+// (n_below = -1 for the first tier, so empty elements are handled there); the last tier
+// puts larger elements on the workgroup kernel's worklist (last != 0).
 template <int PPL, class R>
-__global__ void __launch_bounds__(256) k_element_wave(ElementArgs<R> a)
+__global__ void __launch_bounds__(256) k_element_wave(ElementArgs<R> a, int n_below, int last)
 {
     constexpr int N = 64 * PPL;
     constexpr int RED = (13 * 65 * 8 + 15) & ~15;         // transposed reduction, padded rows
@@ -784,12 +788,13 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs<R> a)
     R* bmean = reinterpret_cast<R*>(base + R1 + 4 * N);
     const int64_t s0 = __builtin_amdgcn_readfirstlane(a.start[e]);
     const int n = __builtin_amdgcn_readfirstlane(a.start[e + 1]) - (int)s0;
+    if (n <= n_below) return;   // an earlier tier's element
     if (n == 0) {
         if (lane < 3 * NPART) a.part[e * 3 * NPART + lane] = R(0);
         return;
     }
     if (n > N) {
-        if (lane == 0) {
+        if (last && lane == 0) {
             const int k = atomicAdd(a.big_count, 1);
             a.big_list[k] = (int32_t)e;
         }
@@ -1328,18 +1333,27 @@ hipError_t prepare_element_pass(int lds_max)
     return hipFuncSetAttribute((const void*)k_element_block<EP_NT, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)element_pass_smem<R>(lds_max));
 }
-template <class R>
-void launch_element_pass(const ElementArgs<R>& a, hipStream_t s)
+template <int PPL, class R>
+static void launch_wave_tier(const ElementArgs<R>& a, int n_below, int last, hipStream_t s)
 {
-    const dim3 g4((unsigned)((a.ne + 3) / 4)), b4(256), g2((unsigned)((a.ne + 1) / 2)), b2(128);
-    switch (a.ppl) {
-    case 1: hipLaunchKernelGGL((k_element_wave<1, R>), g4, b4, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_element_wave<2, R>), g4, b4, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_element_wave<3, R>), g4, b4, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_element_wave<4, R>), g4, b4, 0, s, a); break;
-    case 5: hipLaunchKernelGGL((k_element_wave<5, R>), g4, b4, 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_element_wave<6, R>), g2, b2, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_element_wave<8, R>), g2, b2, 0, s, a); break;
+    constexpr int WPB = WaveBlock<PPL>::waves;
+    hipLaunchKernelGGL((k_element_wave<PPL, R>), dim3((unsigned)((a.ne + WPB - 1) / WPB)), dim3(64 * WPB), 0, s, a,
+                       n_below, last);
+}
+template <class R>
+void launch_element_pass(const ElementArgs<R>& a, const int* tiers, int n_tiers, hipStream_t s)
+{
+    for (int t = 0; t < n_tiers; ++t) {
+        const int n_below = t == 0 ? -1 : 64 * tiers[t - 1], last = t == n_tiers - 1 ? 1 : 0;
+        switch (tiers[t]) {
+        case 1: launch_wave_tier<1, R>(a, n_below, last, s); break;
+        case 2: launch_wave_tier<2, R>(a, n_below, last, s); break;
+        case 3: launch_wave_tier<3, R>(a, n_below, last, s); break;
+        case 4: launch_wave_tier<4, R>(a, n_below, last, s); break;
+        case 5: launch_wave_tier<5, R>(a, n_below, last, s); break;
+        case 6: launch_wave_tier<6, R>(a, n_below, last, s); break;
+        default: launch_wave_tier<8, R>(a, n_below, last, s); break;
+        }
     }
     hipLaunchKernelGGL((k_element_block<EP_NT, R>), dim3(EP_BIG_BLOCKS), dim3(EP_NT), element_pass_smem<R>(a.lds_max),
                        s, a);
@@ -1401,7 +1415,7 @@ void launch_shift_init(const R* node, int64_t nn, R* shift, hipStream_t s)
     template void launch_advance<R>(const AdvanceArgs<R>&, int64_t, bool, int, hipStream_t);             \
     template hipError_t prepare_element_pass<R>(int);                                                    \
     template size_t element_pass_smem<R>(int);                                                           \
-    template void launch_element_pass<R>(const ElementArgs<R>&, hipStream_t);                            \
+    template void launch_element_pass<R>(const ElementArgs<R>&, const int*, int, hipStream_t);          \
     template void launch_node_finalize<R>(const NodeArgs<R>&, hipStream_t);                              \
     template void launch_init<R>(const InitArgs<R>&, hipStream_t);                                       \
     template void launch_ctl_plan<R>(const ControlArgs<R>&, hipStream_t);                                \

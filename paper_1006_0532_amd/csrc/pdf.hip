@@ -142,7 +142,6 @@ pdf_status regroup(pdf_ens_s* E, bool mix, bool counts_ready, bool advance_step,
     ea.ne = g.ne;
     ea.cap = E->cap;
     ea.lds_max = E->lds_max;
-    ea.ppl = E->ppl;
     ea.big_list = E->big_list;
     ea.big_count = E->big_count;
     ea.gkey = E->gkey;
@@ -150,7 +149,7 @@ pdf_status regroup(pdf_ens_s* E, bool mix, bool counts_ready, bool advance_step,
     ea.gu3 = E->gu3;
     {
         Timed t(E, T_ELEMENT, s);
-        launch_element_pass<R>(ea, s);
+        launch_element_pass<R>(ea, E->tiers.data(), (int)E->tiers.size(), s);
     }
     NodeArgs<R> na{};
     na.part = static_cast<const R*>(E->part);
@@ -426,6 +425,25 @@ pdf_status build_devgrid(pdf_ens_s* E, hipStream_t s)
         launch_f64_to_f32(d.node, d.node32, d.nn * NODE_STRIDE, s);
     }
     return PDF_OK;
+}
+
+// particles per lane for a set-up count with 30 % headroom (7 is not instantiated)
+int ppl_for(int64_t ppe)
+{
+    int p = (int)std::min<int64_t>(8, std::max<int64_t>(1, (13 * ppe + 639) / 640));
+    return p == 7 ? 8 : p;
+}
+
+// wavefront tiers from the smallest suggested capacity, doubling, up to ppl
+void set_tiers(pdf_ens_s* E)
+{
+    E->tiers.clear();
+    int t = std::min(E->ppl_min, E->ppl);
+    while (t < E->ppl && (int)E->tiers.size() < 3) {
+        E->tiers.push_back(t);
+        t = t * 2 == 7 ? 8 : std::min(t * 2, 8);
+    }
+    E->tiers.push_back(E->ppl);
 }
 
 // bytes of one state array entry other than x, y, pid, elem
@@ -739,10 +757,14 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
     // element pass: a wavefront per element holds up to 64 * ppl particles (ppl from the
     // largest set-up count with 30 % headroom); larger elements go to the workgroup
     // kernel, whose on-chip path takes up to lds_max particles within 64 KiB of LDS
-    int64_t ppe_max = 1;
-    for (auto& d : E->descs) ppe_max = std::max<int64_t>(ppe_max, d.ppe);
-    E->ppl = (int)std::min<int64_t>(8, std::max<int64_t>(1, (13 * ppe_max + 639) / 640));
-    if (E->ppl == 7) E->ppl = 8;
+    int64_t ppe_max = 1, ppe_min = INT32_MAX;
+    for (auto& d : E->descs) {
+        ppe_max = std::max<int64_t>(ppe_max, d.ppe);
+        if (d.ppe > 0) ppe_min = std::min<int64_t>(ppe_min, d.ppe);
+    }
+    E->ppl = ppl_for(ppe_max);
+    E->ppl_min = ppl_for(ppe_min == INT32_MAX ? ppe_max : ppe_min);
+    set_tiers(E);
     HIP_TRY(hipMemcpyAsync(E->d_prm, E->h_prm.data(), sizeof(ProbParams) * n_problems, hipMemcpyHostToDevice, s));
     st = E->precision == PDF_MIXED ? setup_precision<float>(E, s) : setup_precision<double>(E, s);
     if (st != PDF_OK) {
@@ -1108,6 +1130,7 @@ pdf_status pdf_set_options(pdf_ens E, const pdf_options* opt)
     E->use_graph = opt->use_graph != 0;
     E->adv_block = opt->adv_block;
     E->ppl = opt->ppl;
+    set_tiers(E);
     return PDF_OK;
 }
 

@@ -177,7 +177,9 @@ struct pdf_ens_s {
     hipGraphExec_t gexec[2] = {nullptr, nullptr};   // two steps starting from buffer 0 / 1
     int64_t g_nub[2] = {-1, -1};
     std::vector<double> g_dt[2];
-    int32_t* big_list = nullptr;
+    int32_t* big_list = nullptr;    // [ne] elements left to the workgroup kernel
     int32_t* big_count = nullptr;
+    int ppl_min = 1;                // wavefront capacity suggested by the smallest set-up count
+    std::vector<int> tiers;         // particles per lane of the wavefront tiers, ascending
     bool ctl_valid = false;     // the current buffer holds the canonical order of a pass
 };

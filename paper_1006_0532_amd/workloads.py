@@ -418,10 +418,38 @@ def cavity_huge(nxh=500, ny_channel=1000, ny_cavity=1000, ppe=120, seed=MASTER_S
                                                                      src_y=0.5)
 
 
+def batched_problems(n: int = 64, *, tri_range=(1.0e3, 2.0e5), ppe_range=(20, 400), dt: float = 2e-4,
+                     seed: int = MASTER_SEED):
+    """Independent problems of uneven size for the batched form: triangle counts and
+    particles per element log-uniform in the given ranges, channels for even and street
+    canyons for odd problem seeds, each problem with its own seed.
+    Returns a list of (mesh, fields, model, init, dt)."""
+    rng = np.random.default_rng(seed ^ 0xBA7C4ED)
+    out = []
+    for p in range(n):
+        tri = float(np.exp(rng.uniform(math.log(tri_range[0]), math.log(tri_range[1]))))
+        ppe = int(round(np.exp(rng.uniform(math.log(ppe_range[0]), math.log(ppe_range[1])))))
+        pseed = int(rng.integers(1, 2 ** 62))
+        if pseed % 2 == 0:
+            ny = max(4, 2 * int(round(math.sqrt(tri / 2.0 / 1.6) / 2.0)))
+            nx = max(4, int(round(tri / 2.0 / ny)))
+            mesh = channel_mesh(nx, ny, seed=pseed)
+            fields = channel_fields(mesh)
+            init = init_desc(ppe=ppe, bins=(4, 2, 2), seed=pseed)
+        else:
+            nxh = max(2, int(round(math.sqrt(tri / 16.0))))
+            mesh = cavity_mesh(nxh, 2 * nxh, 2 * nxh, seed=pseed)
+            fields = cavity_fields(mesh)
+            init = init_desc(ppe=ppe, bins=(4, 2, 2), src_x=1.5, src_y=0.5, seed=pseed)
+        out.append((mesh, fields, model_constants(), init, dt))
+    return out
+
+
 WORKLOADS = {
     "channel_small": dict(fn=channel_small, dt=1e-3, steps=20, control=None),
     "channel_large": dict(fn=channel_large, dt=2e-4, steps=100, control=(150, 250)),
     "cavity_small": dict(fn=cavity_small, dt=1e-4, steps=20, control=None),
     "cavity_large": dict(fn=cavity_large, dt=1e-4, steps=200, control=None),
     "cavity_huge": dict(fn=cavity_huge, dt=1e-4, steps=500, control=(90, 150)),
+    "batched_64": dict(fn=batched_problems, dt=2e-4, steps=50, control=None),
 }
