@@ -81,6 +81,7 @@ pdf_status build_grid(pdf_grid_s& g, const pdf_mesh_desc& m, const pdf_fields_de
                 if (G.x[k] < 0.5 * P) G.x[k] += P;
         G.area = 0.5 * ((G.x[1] - G.x[0]) * (G.y[2] - G.y[0]) - (G.y[1] - G.y[0]) * (G.x[2] - G.x[0]));
         if (!(G.area > 0.0)) { set_error("pdf_grid_create: element not counter-clockwise or degenerate"); return PDF_E_MESH; }
+        G.inv_area = 1.0 / G.area;
     }
 
     // neighbours: sort all directed edges by their node pair

@@ -28,6 +28,8 @@ struct AdvanceArgs {
     uint32_t* err;
     unsigned long long* cnt;    // [problem][NCOUNT][CNT_SLOTS]
     const int64_t* meta;        // [0] used slots, [4] step counter
+    int32_t* wall_list;         // [cap] slots that take a new frequency (no-slip events)
+    int32_t* wall_count;
     int64_t ne;
     ProbParams p0;              // parameters of problem 0 (single-problem ensembles)
     const ProbParams* prm;      // [n_problems] (batched ensembles)
@@ -65,7 +67,7 @@ struct NodeArgs {
     const int32_t* start;
     int64_t ne;
     int64_t* meta;
-    int32_t* big_count;
+    int32_t* big_count;     // [2] large-element worklist, no-slip resample list
     int32_t advance_step;   // 1 after a time step: the device step counter moves on
 };
 

@@ -50,6 +50,7 @@ __device__ __noinline__ bool fallback_search(const ElemGeo* __restrict__ geo, co
 
 struct AdvEvents {
     int ev_a, ev_b, omrefl, clamp, src, steps, refl, fb;
+    int resample;   // the frequency is drawn again after the loop (no-slip event)
 };
 
 // One particle of the particle loop.  Returns its new host element (its old one when it
@@ -127,7 +128,6 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
     const R sdt = M::sqrt_(dt);
     const R dWx = sdt * z0, dWy = sdt * z1;
     const R dWp0 = sdt * z2, dWp1 = sdt * z3, dWp2 = sdt * z4, dWo = sdt * z5;
-    const R eta = M::uni(wB.w2);
     const R s2nu = M::sqrt_(R(2) * nu);
     const R sc0 = M::sqrt_(c0eps);
 
@@ -223,7 +223,8 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
         atomicOr(a.err, ERR_LOST);
         return e;   // the particle keeps its start-of-step state
     }
-    // no-slip events: (a) crossed the wall; (b) Eq. (53) in wall elements
+    // no-slip events: (a) crossed the wall; (b) Eq. (53) in wall elements.  The test is a
+    // discrete decision on positions: FP64 in both forms.
     bool hit = wall_a != 0;
     const ElemGeo* C = a.geo + c;
     if (!hit && C->wall && P.m.nu * P.dt > 0.0) {
@@ -231,8 +232,8 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
         double dn1 = (x - C->wl[0]) * C->wl[2] + (y - C->wl[1]) * C->wl[3];
         dn = dn < 0.0 ? 0.0 : dn;
         dn1 = dn1 < 0.0 ? 0.0 : dn1;
-        const R fw = M::exp_((R)(-dn * dn1 / (P.m.nu * P.dt)));
-        if (eta < fw) {
+        const double fw = exp(-dn * dn1 / (P.m.nu * P.dt));
+        if (u01(wB.w2) < fw) {
             hit = true;
             ev.ev_b = 1;
         }
@@ -247,7 +248,10 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
         const R omw = (R)(pa_ / C->area) * HA[NF_OM] + (R)(pb_ / C->area) * HB[NF_OM] +
                       (R)(pc_ / C->area) * HC[NF_OM];
         v0 = v1 = v2 = R(0);
-        omn = gamma_draw<R>(R(1) / C4, omw, P.key, pid, step, TAG_WALL_GAMMA);
+        // Eq. (58): omega ~ Gamma with this mean, drawn by k_wall_resample (the sampler is
+        // kept out of the particle loop, whose register budget it would set)
+        omn = omw;
+        ev.resample = 1;
     }
     a.s.x[i] = x;
     a.s.y[i] = y;
@@ -338,14 +342,14 @@ __device__ __forceinline__ void count_new_hosts(int32_t* __restrict__ counts, in
 
 // Particle loop: one thread per used slot (merged particles are dead slots, elem < 0)
 template <class R, bool BATCHED>
-__global__ void __launch_bounds__(256) k_advance(AdvanceArgs<R> a)
+__device__ __forceinline__ void particle_loop(const AdvanceArgs<R>& a)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nslots = a.meta[0];
     const uint32_t step = (uint32_t)a.meta[4];
     int32_t key = -1;
     int prob = -1;
-    AdvEvents ev = {0, 0, 0, 0, 0, 0, 0, 0};
+    AdvEvents ev = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < nslots) {
         int32_t e = a.s.elem[i];
         if (e >= a.ne) {
@@ -354,8 +358,49 @@ __global__ void __launch_bounds__(256) k_advance(AdvanceArgs<R> a)
         }
         if (e >= 0) key = advance_one<R, BATCHED>(a, i, e, step, ev, prob);
     }
+    // slots whose frequency is drawn again: one atomic per wavefront
+    const unsigned long long rm = __ballot(ev.resample != 0);
+    if (rm) {
+        const int lane = lane_id();
+        int base = 0;
+        if (lane == 0) base = atomicAdd(a.wall_count, __popcll(rm));
+        base = __shfl(base, 0);
+        if (ev.resample) a.wall_list[base + __popcll(rm & ((1ull << lane) - 1ull))] = (int32_t)i;
+    }
     count_new_hosts(a.counts, key);
     flush_events<BATCHED>(a.cnt, ev, prob);
+}
+
+// One problem: three wavefronts per SIMD (at most 168 registers; the FP64 form spills a
+// few values of its cold paths).
+template <class R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_advance(AdvanceArgs<R> a)
+{
+    particle_loop<R, false>(a);
+}
+
+// Several problems: per-particle problem parameters from the table
+template <class R>
+__global__ void __launch_bounds__(256) k_advance_batched(AdvanceArgs<R> a)
+{
+    particle_loop<R, true>(a);
+}
+
+// Eq. (58) for the particles of the last no-slip events: omega ~ Gamma(1/C4) with the mean
+// the particle loop left in omega.  The sampler's accept / reject decisions are FP64 in
+// both forms.
+template <class R>
+__global__ void __launch_bounds__(256) k_wall_resample(SoaT<R> s, const int32_t* __restrict__ list,
+                                                       const int32_t* __restrict__ count, const ElemGeo* __restrict__ geo,
+                                                       const ProbParams* __restrict__ prm, const int64_t* __restrict__ meta)
+{
+    const int n = *count;
+    const uint32_t step = (uint32_t)meta[4];
+    for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
+        const int64_t i = list[j];
+        const ProbParams& P = prm[geo[s.elem[i]].prob];
+        s.om[i] = (R)gamma_draw<double>(1.0 / P.m.C4, (double)s.om[i], P.key, s.pid[i], step, TAG_WALL_GAMMA);
+    }
 }
 
 // =====================================================================================
@@ -459,28 +504,44 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const int32_t* __restric
     if (blockIdx.x == nb - 1 && threadIdx.x == SCAN_NT - 1) out[n] = run;
 }
 
-// slot of every live particle inside its element's segment; the counts return to zero
+// Slot of every live particle inside its element's segment; the counts return to zero.
+// A workgroup covers SCAT_ROUNDS x 256 consecutive slots: every wavefront issues the
+// returning atomics of all its rounds before it waits for the first result.
+constexpr int SCAT_ROUNDS = 4;
 __global__ void __launch_bounds__(256) k_scatter(const int32_t* __restrict__ elem, const int64_t* __restrict__ nslots,
                                                  int64_t ne, int32_t* __restrict__ counts,
                                                  const int32_t* __restrict__ start, int32_t* __restrict__ idx,
                                                  uint32_t* __restrict__ err)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int32_t key = -1;
-    if (i < *nslots) {
-        key = elem[i];
-        if (key >= ne) key = -1;
+    const int64_t ns = *nslots;
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    const int64_t first = (int64_t)blockIdx.x * (256 * SCAT_ROUNDS) + (int64_t)wid * (64 * SCAT_ROUNDS) + lane;
+    int32_t key[SCAT_ROUNDS];
+    int leader[SCAT_ROUNDS], len[SCAT_ROUNDS], rank[SCAT_ROUNDS], base[SCAT_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < SCAT_ROUNDS; ++r) {
+        const int64_t i = first + 64 * r;
+        key[r] = -1;
+        if (i < ns) {
+            key[r] = elem[i];
+            if (key[r] >= ne) key[r] = -1;
+        }
     }
-    int leader, len, rank;
-    wave_runs(key, leader, len, rank);
-    int base = 0;
-    if (rank == 0 && key >= 0) base = atomicSub(counts + key, len) - len;
-    base = __shfl(base, leader);
-    if (key >= 0) {
-        const int64_t lo = start[key], hi = start[key + 1];
-        const int64_t slot = lo + (int64_t)base + rank;
-        if (slot >= lo && slot < hi) idx[slot] = (int32_t)i;
-        else atomicOr(err, ERR_BADELEM);
+#pragma unroll
+    for (int r = 0; r < SCAT_ROUNDS; ++r) {
+        wave_runs(key[r], leader[r], len[r], rank[r]);
+        base[r] = 0;
+        if (rank[r] == 0 && key[r] >= 0) base[r] = atomicSub(counts + key[r], len[r]) - len[r];
+    }
+#pragma unroll
+    for (int r = 0; r < SCAT_ROUNDS; ++r) {
+        const int b = __shfl(base[r], leader[r]);
+        if (key[r] >= 0) {
+            const int64_t lo = start[key[r]], hi = start[key[r] + 1];
+            const int64_t slot = lo + (int64_t)b + rank[r];
+            if (slot >= lo && slot < hi) idx[slot] = (int32_t)(first + 64 * r);
+            else atomicOr(err, ERR_BADELEM);
+        }
     }
 }
 
@@ -645,7 +706,7 @@ __device__ __forceinline__ void element_body(const ElementArgs<R>& a, int32_t e,
 
     // IECM (Eq. 24); statistics partials; canonical write-out
     const R fmix = (R)mix_fraction(a.mix, P.dt, a.tm[e]);
-    const double inv_area = 1.0 / G->area;
+    const double inv_area = G->inv_area;
     R rs[3][5];
 #pragma unroll
     for (int v = 0; v < 3; ++v)
@@ -934,7 +995,7 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs<R> a, int n_be
     wave_sync();
 
     const R fmix = (R)mix_fraction(a.mix, P.dt, a.tm[e]);
-    const double inv_area = 1.0 / G->area;
+    const double inv_area = G->inv_area;
     R rs[3][5];
 #pragma unroll
     for (int v = 0; v < 3; ++v)
@@ -995,7 +1056,8 @@ __global__ void __launch_bounds__(256) k_node_finalize(NodeArgs<R> a)
         a.meta[0] = a.start[a.ne];   // used slots after compaction
         a.meta[1] = a.start[a.ne];   // live particles
         if (a.advance_step) a.meta[4] += 1;   // step counter of the random streams
-        *a.big_count = 0;            // worklist of large elements, empty for the next pass
+        a.big_count[0] = 0;          // worklist of large elements, empty for the next pass
+        a.big_count[1] = 0;          // list of no-slip resamples, empty for the next step
     }
     if (i >= a.nn) return;
     Acc<R> S[NPART];
@@ -1064,7 +1126,7 @@ __global__ void __launch_bounds__(256) k_init(InitArgs<R> a)
     const double y = G->y[0] + s * (G->y[1] - G->y[0]) + t * (G->y[2] - G->y[0]);
     double na, nb, nc;
     area_coords(G, x, y, na, nb, nc);
-    const R la = (R)(na / G->area), lb = (R)(nb / G->area), lc = (R)(nc / G->area);
+    const R la = (R)(na * G->inv_area), lb = (R)(nb * G->inv_area), lc = (R)(nc * G->inv_area);
     const R* FA = a.node + (int64_t)G->node[0] * NODE_STRIDE;
     const R* FB = a.node + (int64_t)G->node[1] * NODE_STRIDE;
     const R* FC = a.node + (int64_t)G->node[2] * NODE_STRIDE;
@@ -1081,7 +1143,7 @@ __global__ void __launch_bounds__(256) k_init(InitArgs<R> a)
     a.s.u0[i] = mu0 + sig * z0;
     a.s.u1[i] = mu1 + sig * z1;
     a.s.u2[i] = mu2 + sig * z2;
-    a.s.om[i] = gamma_draw<R>((R)P.omega_shape, omm, P.key, pid, 0, TAG_INIT_GAMMA);
+    a.s.om[i] = (R)gamma_draw<double>(P.omega_shape, (double)omm, P.key, pid, 0, TAG_INIT_GAMMA);
     double dx = x - P.src_x, dy = y - P.src_y;
     if (P.period > 0.0) {
         if (dx > 0.5 * P.period) dx -= P.period;
@@ -1297,9 +1359,11 @@ void launch_advance(const AdvanceArgs<R>& a, int64_t n_ub, bool batched, int blo
     if (n_ub <= 0) return;
     if (block != 64 && block != 128) block = 256;
     if (batched)
-        hipLaunchKernelGGL((k_advance<R, true>), dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
+        hipLaunchKernelGGL(k_advance_batched<R>, dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
     else
-        hipLaunchKernelGGL((k_advance<R, false>), dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
+        hipLaunchKernelGGL(k_advance<R>, dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
+    hipLaunchKernelGGL(k_wall_resample<R>, dim3(256), dim3(256), 0, s, a.s, (const int32_t*)a.wall_list,
+                       (const int32_t*)a.wall_count, a.geo, a.prm, a.meta);
 }
 void launch_count(const int32_t* elem, const int64_t* nslots, int64_t n_ub, int64_t ne, int32_t* counts,
                   uint32_t* err, hipStream_t s)
@@ -1325,7 +1389,8 @@ void launch_scatter(const int32_t* elem, const int64_t* nslots, int64_t n_ub, in
                     const int32_t* start, int32_t* idx, uint32_t* err, hipStream_t s)
 {
     if (n_ub > 0)
-        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n_ub, 256)), dim3(256), 0, s, elem, nslots, ne, counts, start, idx, err);
+        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n_ub, 256 * SCAT_ROUNDS)), dim3(256), 0, s, elem, nslots, ne, counts,
+                           start, idx, err);
 }
 template <class R>
 hipError_t prepare_element_pass(int lds_max)

@@ -193,6 +193,8 @@ pdf_status step_once(pdf_ens_s* E, hipStream_t s)
     a.err = E->err;
     a.cnt = E->cnt;
     a.meta = E->d_meta;
+    a.wall_list = E->idx;          // free between the particle loop and the scatter
+    a.wall_count = E->big_count + 1;
     a.ne = g.ne;
     a.p0 = E->h_prm[0];
     a.prm = E->d_prm;
@@ -749,7 +751,7 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
     if (st == PDF_OK) st = dalloc(&E->ctl_off, g.ne + 1);
     if (st == PDF_OK) st = dalloc(&E->ctl_rep, 4);
     if (st == PDF_OK) st = dalloc(&E->big_list, g.ne);
-    if (st == PDF_OK) st = dalloc(&E->big_count, 1);
+    if (st == PDF_OK) st = dalloc(&E->big_count, 2);
     if (st != PDF_OK) {
         pdf_ens_destroy(E);
         return st;
@@ -772,7 +774,7 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
         return st;
     }
     launch_fill_i32(E->counts, g.ne, 0, s);
-    launch_fill_i32(E->big_count, 1, 0, s);
+    launch_fill_i32(E->big_count, 2, 0, s);
     launch_fill_i32(E->idx, cap, 0, s);
     launch_fill_u64(E->cnt, (int64_t)n_problems * NCOUNT * CNT_SLOTS, 0ull, s);
     launch_fill_i32(reinterpret_cast<int32_t*>(E->err), 1, 0, s);

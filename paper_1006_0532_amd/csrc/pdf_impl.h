@@ -22,6 +22,7 @@ enum : uint8_t { KIND_INTERIOR = 0, KIND_WALL = 1, KIND_SLIP = 2, KIND_PERIODIC 
 struct __attribute__((aligned(16))) ElemGeo {
     double x[3], y[3];  // vertices in the element's own frame (seam elements unwrapped)
     double area;        // A_e > 0
+    double inv_area;    // 1 / A_e
     double shift[3];    // x shift added when leaving through a periodic edge
     double gu[6];       // d<U1>/dx, d<U1>/dy, d<U2>/dx, d<U2>/dy, d<U3>/dx, d<U3>/dy
     double wl[4];       // wall line: point (x, y) and inward unit normal (x, y)
@@ -178,7 +179,7 @@ struct pdf_ens_s {
     int64_t g_nub[2] = {-1, -1};
     std::vector<double> g_dt[2];
     int32_t* big_list = nullptr;    // [ne] elements left to the workgroup kernel
-    int32_t* big_count = nullptr;
+    int32_t* big_count = nullptr;   // [2] large elements, no-slip resamples
     int ppl_min = 1;                // wavefront capacity suggested by the smallest set-up count
     std::vector<int> tiers;         // particles per lane of the wavefront tiers, ascending
     bool ctl_valid = false;     // the current buffer holds the canonical order of a pass

@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpdfgpu.so")
+LIB_PATH = os.environ.get("PDFGPU_LIB") or os.path.join(HERE, "libpdfgpu.so")
 
 PDF_NSTAT = 13
 PDF_NCOUNTERS = 8
