@@ -82,6 +82,7 @@ def lib():
         "orc_import": (C.c_int32, [P, C.c_int64, dp, dp, dp, dp, dp, dp, u64p, ip, C.c_int64, C.c_uint64]),
         "orc_stats": (C.c_int32, [P, dp]),
         "orc_refresh_stats": (C.c_int32, [P]),
+        "orc_feedback": (C.c_int32, [P, C.c_double, C.c_int32]),
         "orc_control": (C.c_int32, [P, C.c_int32, C.c_int32, i64p]),
         "orc_counters": (None, [P, i64p]),
         "orc_bin_element": (C.c_int32, [C.c_int32, dp, u64p, ip, C.c_int32, ip, ip]),
@@ -256,6 +257,14 @@ class Ensemble:
         if rc != 0:
             raise RuntimeError(f"oracle stats failed: {rc}")
         return out
+
+    def feedback(self, alpha: float, feed_rey: bool = False):
+        """Nodal statistics of the last step become the grid's fields (mean velocity scaled
+        by alpha, Reynolds stresses when feed_rey); gradients and Laplacians are derived
+        again.  The grid is modified."""
+        rc = lib().orc_feedback(self.h, float(alpha), int(bool(feed_rey)))
+        if rc != 0:
+            raise RuntimeError(f"orc_feedback: {rc}")
 
     def refresh_stats(self):
         lib().orc_refresh_stats(self.h)

@@ -241,6 +241,60 @@ static int finite_all(const double* a, int64_t n)
     return 1;
 }
 
+/* Fields derived from the nodal mean velocity: element gradients (Eqs. 39-40) and the
+   two-pass nodal Laplacian (Sec. 3.4). */
+static void derive_fields(orc_grid* g)
+{
+    const int64_t nn = g->nn, ne = g->ne;
+    const int32_t* tri = g->tri;
+    /* element gradients of <U_i> (Eqs. 39-40), constant per element */
+    for (int64_t e = 0; e < ne; ++e) {
+        const int32_t* t = tri + 3 * e;
+        for (int i = 0; i < 3; ++i)
+            elem_grad(g, (int32_t)e, g->F[(int64_t)t[0] * NF + F_MU + i], g->F[(int64_t)t[1] * NF + F_MU + i],
+                      g->F[(int64_t)t[2] * NF + F_MU + i], &g->gU[6 * e + 2 * i], &g->gU[6 * e + 2 * i + 1]);
+    }
+
+    /* second derivatives by the two-pass procedure of Sec. 3.4: element gradients are
+       averaged to the nodes over the surrounding elements; the gradients of those nodal
+       gradients are averaged to the nodes again.  lap<U_i> = d2/dx2 + d2/dy2. */
+    {
+        double* gn = (double*)calloc(6 * nn, sizeof(double));
+        for (int64_t n = 0; n < nn; ++n) {
+            int64_t cnt = g->n2e_ptr[n + 1] - g->n2e_ptr[n];
+            for (int64_t j = g->n2e_ptr[n]; j < g->n2e_ptr[n + 1]; ++j)
+                for (int q = 0; q < 6; ++q) gn[6 * n + q] += g->gU[6 * (int64_t)g->n2e[j] + q];
+            if (cnt > 0) for (int q = 0; q < 6; ++q) gn[6 * n + q] /= (double)cnt;
+        }
+        /* per element: d/dx of (dU_i/dx) and d/dy of (dU_i/dy) */
+        double* h = (double*)malloc(sizeof(double) * 6 * ne);
+        for (int64_t e = 0; e < ne; ++e) {
+            const int32_t* t = tri + 3 * e;
+            for (int i = 0; i < 3; ++i) {
+                double dxx, dxy, dyx, dyy;
+                elem_grad(g, (int32_t)e, gn[6 * (int64_t)t[0] + 2 * i], gn[6 * (int64_t)t[1] + 2 * i], gn[6 * (int64_t)t[2] + 2 * i], &dxx, &dxy);
+                elem_grad(g, (int32_t)e, gn[6 * (int64_t)t[0] + 2 * i + 1], gn[6 * (int64_t)t[1] + 2 * i + 1], gn[6 * (int64_t)t[2] + 2 * i + 1], &dyx, &dyy);
+                h[6 * e + 2 * i] = dxx;
+                h[6 * e + 2 * i + 1] = dyy;
+            }
+        }
+        for (int64_t n = 0; n < nn; ++n) {
+            int64_t cnt = g->n2e_ptr[n + 1] - g->n2e_ptr[n];
+            for (int i = 0; i < 3; ++i) {
+                double sxx = 0, syy = 0;
+                for (int64_t j = g->n2e_ptr[n]; j < g->n2e_ptr[n + 1]; ++j) {
+                    sxx += h[6 * (int64_t)g->n2e[j] + 2 * i];
+                    syy += h[6 * (int64_t)g->n2e[j] + 2 * i + 1];
+                }
+                g->F[n * NF + F_LAP + i] = cnt > 0 ? sxx / (double)cnt + syy / (double)cnt : 0.0;
+            }
+        }
+        free(h);
+        free(gn);
+    }
+
+}
+
 orc_grid* orc_grid_create(int64_t nn, const double* xy, int64_t ne, const int32_t* tri,
                           const uint8_t* edge_kind, double period_x,
                           const double* grad_p, const double* wp, const double* mean_u,
@@ -348,51 +402,7 @@ orc_grid* orc_grid_create(int64_t nn, const double* xy, int64_t ne, const int32_
         if (!(f[F_RE] + f[F_RE + 1] + f[F_RE + 2] > 0.0)) { seterr(err, errlen, "kinetic energy must be positive"); orc_grid_destroy(g); return NULL; }
     }
 
-    /* element gradients of <U_i> (Eqs. 39-40), constant per element */
-    for (int64_t e = 0; e < ne; ++e) {
-        const int32_t* t = tri + 3 * e;
-        for (int i = 0; i < 3; ++i)
-            elem_grad(g, (int32_t)e, g->F[(int64_t)t[0] * NF + F_MU + i], g->F[(int64_t)t[1] * NF + F_MU + i],
-                      g->F[(int64_t)t[2] * NF + F_MU + i], &g->gU[6 * e + 2 * i], &g->gU[6 * e + 2 * i + 1]);
-    }
-
-    /* second derivatives by the two-pass procedure of Sec. 3.4: element gradients are
-       averaged to the nodes over the surrounding elements; the gradients of those nodal
-       gradients are averaged to the nodes again.  lap<U_i> = d2/dx2 + d2/dy2. */
-    {
-        double* gn = (double*)calloc(6 * nn, sizeof(double));
-        for (int64_t n = 0; n < nn; ++n) {
-            int64_t cnt = g->n2e_ptr[n + 1] - g->n2e_ptr[n];
-            for (int64_t j = g->n2e_ptr[n]; j < g->n2e_ptr[n + 1]; ++j)
-                for (int q = 0; q < 6; ++q) gn[6 * n + q] += g->gU[6 * (int64_t)g->n2e[j] + q];
-            if (cnt > 0) for (int q = 0; q < 6; ++q) gn[6 * n + q] /= (double)cnt;
-        }
-        /* per element: d/dx of (dU_i/dx) and d/dy of (dU_i/dy) */
-        double* h = (double*)malloc(sizeof(double) * 6 * ne);
-        for (int64_t e = 0; e < ne; ++e) {
-            const int32_t* t = tri + 3 * e;
-            for (int i = 0; i < 3; ++i) {
-                double dxx, dxy, dyx, dyy;
-                elem_grad(g, (int32_t)e, gn[6 * (int64_t)t[0] + 2 * i], gn[6 * (int64_t)t[1] + 2 * i], gn[6 * (int64_t)t[2] + 2 * i], &dxx, &dxy);
-                elem_grad(g, (int32_t)e, gn[6 * (int64_t)t[0] + 2 * i + 1], gn[6 * (int64_t)t[1] + 2 * i + 1], gn[6 * (int64_t)t[2] + 2 * i + 1], &dyx, &dyy);
-                h[6 * e + 2 * i] = dxx;
-                h[6 * e + 2 * i + 1] = dyy;
-            }
-        }
-        for (int64_t n = 0; n < nn; ++n) {
-            int64_t cnt = g->n2e_ptr[n + 1] - g->n2e_ptr[n];
-            for (int i = 0; i < 3; ++i) {
-                double sxx = 0, syy = 0;
-                for (int64_t j = g->n2e_ptr[n]; j < g->n2e_ptr[n + 1]; ++j) {
-                    sxx += h[6 * (int64_t)g->n2e[j] + 2 * i];
-                    syy += h[6 * (int64_t)g->n2e[j] + 2 * i + 1];
-                }
-                g->F[n * NF + F_LAP + i] = cnt > 0 ? sxx / (double)cnt + syy / (double)cnt : 0.0;
-            }
-        }
-        free(h);
-        free(gn);
-    }
+    derive_fields(g);
 
     /* wall elements (Sec. 3.8: elements with an edge or a node on a no-slip wall) and
        the line of the wall edge, among the wall edges touching the element's nodes,
@@ -1121,5 +1131,28 @@ int32_t orc_control(orc_ens* E, int32_t n_min, int32_t n_max, int64_t* report)
         report[4] = below; report[5] = above;
     }
     free(nclone);
+    return 0;
+}
+
+/* Statistics feedback (Sec. 3.1, Table 1: a time step uses the Eulerian statistics of the
+   step before).  The nodal mean velocity of the last statistics, scaled by alpha (the
+   alpha of Eq. 47 in the redistribution test of Sec. 3.7), becomes the nodal <U> field;
+   with feed_rey the Reynolds stresses become the nodal R field where their trace is
+   positive.  Nodes without particles (W = 0) keep their fields.  Element gradients and
+   Laplacians are derived again from the new <U>.  The micromixing time scale keeps its
+   set-up value. */
+int32_t orc_feedback(orc_ens* E, double alpha, int32_t feed_rey)
+{
+    if (!E->have_stats) return ORC_E_STATE;
+    orc_grid* g = E->g;
+    for (int64_t n = 0; n < g->nn; ++n) {
+        const double* o = E->stats + n * NSTAT;
+        double* f = g->F + n * NF;
+        if (!(o[0] > 0.0)) continue;
+        for (int q = 0; q < 3; ++q) f[F_MU + q] = alpha * o[1 + q];
+        if (feed_rey && o[6] + o[7] + o[8] > 0.0)
+            for (int q = 0; q < 6; ++q) f[F_RE + q] = o[6 + q];
+    }
+    derive_fields(g);
     return 0;
 }

@@ -418,6 +418,23 @@ def cavity_huge(nxh=500, ny_channel=1000, ny_cavity=1000, ppe=120, seed=MASTER_S
                                                                      src_y=0.5)
 
 
+def redistribution_test(nx: int = 16, ny: int = 24, *, stretch: float = 50.0, ppe: int = 200,
+                        mean0=(1.0, 0.0, 0.0), seed: int = MASTER_SEED):
+    """The particle-redistribution test of Sec. 3.7 (Eqs. 46-48) in the form of Eq. (27):
+    a periodic strip with free-slip walls whose cells are stretched towards both walls;
+    nu = 0, grad<P> = 0 and frozen <omega> = 1, R = 2 I, wp = -1.5 I, so that
+    G = (wp - eps/2 I)/k = -I and C0 eps = -2/3 wp:R/k = 2, i.e. dU = -(U - <U>)dt +
+    sqrt(2) dW.  Feeding the nodal mean velocity back scaled by alpha gives Eq. (47).
+    Particles start with unit-variance Gaussian velocities about mean0."""
+    mesh = channel_mesh(nx, ny, length=2.0, y0=-1.0, y1=1.0, stretch=stretch, jitter=0.1, seed=seed,
+                        bottom=EDGE_SLIP, top=EDGE_SLIP)
+    fields = uniform_fields(mesh, grad_p=(0.0, 0.0), wp=(-1.5, -1.5, -1.5, 0.0, 0.0, 0.0),
+                            mean_u=tuple(mean0), mean_omega=1.0, rey=(2.0, 2.0, 2.0, 0.0, 0.0, 0.0))
+    init = init_desc(ppe=ppe, u_sigma=1.0, omega_shape=4.0, src_x=1.0, src_y=0.0, src_r=0.2,
+                     bins=(4, 2, 2), seed=seed)
+    return mesh, fields, model_constants(nu=0.0), init
+
+
 def batched_problems(n: int = 64, *, tri_range=(1.0e3, 2.0e5), ppe_range=(20, 400), dt: float = 2e-4,
                      seed: int = MASTER_SEED):
     """Independent problems of uneven size for the batched form: triangle counts and
