@@ -227,6 +227,17 @@ pdf_status pdf_counters(pdf_ens ens, int32_t problem, int64_t out[PDF_NCOUNTERS]
  * count, other.  Synchronises when reading. */
 pdf_status pdf_timing(pdf_ens ens, int32_t enable, double* ms_out, int64_t* launches_out);
 
+/* Statistics feedback (Sec. 3.1, Table 1 order: a step uses the Eulerian statistics of the
+ * step before).  enable != 0: the nodal mean velocity of the current statistics, scaled
+ * by alpha (the alpha of Eq. 47 in the redistribution test of Sec. 3.7; 1 for plain
+ * feedback), and with feed_rey the Reynolds stresses (where their trace is positive)
+ * become the ensemble's nodal <U> and R fields, now and after every later step; element
+ * gradients (Eq. 40) and nodal Laplacians (Sec. 3.4) of <U> are derived again.  Nodes
+ * without particles keep their fields; the micromixing time scale keeps its set-up value.
+ * The ensemble works on its own copy of the fields (the grid is not modified).
+ * enable = 0 stops the feedback and keeps the current fields.  Synchronises. */
+pdf_status pdf_set_feedback(pdf_ens ens, int32_t enable, double alpha, int32_t feed_rey, void* hip_stream);
+
 /* Launch options of an ensemble; none changes any result.
  *  use_graph  1: pdf_step replays every two steps from a captured HIP graph on a
  *             stream of the ensemble (ordered after and before hip_stream by events),

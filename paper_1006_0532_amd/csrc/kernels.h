@@ -130,6 +130,10 @@ void launch_tm(const ElemGeo* geo, const double* node, int64_t ne, const ProbPar
                hipStream_t s);
 void launch_ctl_finish(int64_t* meta, const int32_t* off, int64_t ne, const unsigned long long* rep, int64_t cap,
                        ProbParams* prm, int32_t n_problems, hipStream_t s);
+// statistics feedback: nodal <U> (scaled by alpha) and optionally R from the statistics,
+// then element gradients and nodal Laplacians of <U>; gn [6 nn] and h [6 ne] are scratch
+void launch_feedback(const double* stats, double* node, ElemGeo* geo, const int64_t* n2e_ptr, const int32_t* n2e,
+                     int64_t nn, int64_t ne, double alpha, int32_t rey, double* gn, double* h, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 void launch_f64_to_f32(const double* in, float* out, int64_t n, hipStream_t s);

@@ -1349,6 +1349,94 @@ __global__ void __launch_bounds__(256) k_shift_init(const R* __restrict__ node, 
 }
 
 // =====================================================================================
+// statistics feedback (Sec. 3.1, Table 1 order: a step uses the statistics of the step
+// before): nodal fields from the last statistics, then the derived fields again
+// =====================================================================================
+// nodal <U> <- alpha * mean velocity; R <- Reynolds stresses (trace > 0); nodes without
+// particles keep their fields
+__global__ void __launch_bounds__(256) k_fb_nodes(const double* __restrict__ stats, double* __restrict__ node,
+                                                  int64_t nn, double alpha, int32_t rey)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nn) return;
+    const double* o = stats + i * NSTAT;
+    double* f = node + i * NODE_STRIDE;
+    if (!(o[0] > 0.0)) return;
+    for (int q = 0; q < 3; ++q) f[NF_MU + q] = alpha * o[1 + q];
+    if (rey && o[6] + o[7] + o[8] > 0.0)
+        for (int q = 0; q < 6; ++q) f[NF_RE + q] = o[6 + q];
+}
+
+// gradient of a P1 field from its vertex values (Eqs. 39-40), in the element's frame
+__device__ __forceinline__ void p1_grad(const ElemGeo& G, double qa, double qb, double qc, double& gx, double& gy)
+{
+    const double xba = G.x[1] - G.x[0], xca = G.x[2] - G.x[0];
+    const double yba = G.y[1] - G.y[0], yca = G.y[2] - G.y[0];
+    const double inv2a = 1.0 / (2.0 * G.area);
+    gx = inv2a * ((yba - yca) * qa + yca * qb - yba * qc);
+    gy = inv2a * ((xca - xba) * qa - xca * qb + xba * qc);
+}
+
+__global__ void __launch_bounds__(256) k_fb_grad(ElemGeo* __restrict__ geo, const double* __restrict__ node, int64_t ne)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= ne) return;
+    ElemGeo& G = geo[e];
+    for (int i = 0; i < 3; ++i)
+        p1_grad(G, node[(int64_t)G.node[0] * NODE_STRIDE + NF_MU + i], node[(int64_t)G.node[1] * NODE_STRIDE + NF_MU + i],
+                node[(int64_t)G.node[2] * NODE_STRIDE + NF_MU + i], G.gu[2 * i], G.gu[2 * i + 1]);
+}
+
+// two-pass second derivatives (Sec. 3.4): element gradients averaged to the nodes ...
+__global__ void __launch_bounds__(256) k_fb_gn(const ElemGeo* __restrict__ geo, const int64_t* __restrict__ n2e_ptr,
+                                               const int32_t* __restrict__ n2e, int64_t nn, double* __restrict__ gn)
+{
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= nn) return;
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    const int64_t j0 = n2e_ptr[n], j1 = n2e_ptr[n + 1];
+    for (int64_t j = j0; j < j1; ++j)
+        for (int q = 0; q < 6; ++q) s[q] += geo[n2e[j] / 3].gu[q];
+    const double c = (double)(j1 - j0);
+    for (int q = 0; q < 6; ++q) gn[6 * n + q] = j1 > j0 ? s[q] / c : 0.0;
+}
+
+// ... their element gradients (d/dx of the x-derivative, d/dy of the y-derivative) ...
+__global__ void __launch_bounds__(256) k_fb_h(const ElemGeo* __restrict__ geo, const double* __restrict__ gn, int64_t ne,
+                                              double* __restrict__ h)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= ne) return;
+    const ElemGeo& G = geo[e];
+    const int64_t a = G.node[0], b = G.node[1], c = G.node[2];
+    for (int i = 0; i < 3; ++i) {
+        double dxx, dxy, dyx, dyy;
+        p1_grad(G, gn[6 * a + 2 * i], gn[6 * b + 2 * i], gn[6 * c + 2 * i], dxx, dxy);
+        p1_grad(G, gn[6 * a + 2 * i + 1], gn[6 * b + 2 * i + 1], gn[6 * c + 2 * i + 1], dyx, dyy);
+        h[6 * e + 2 * i] = dxx;
+        h[6 * e + 2 * i + 1] = dyy;
+    }
+}
+
+// ... averaged to the nodes again: lap<U_i> = d2/dx2 + d2/dy2
+__global__ void __launch_bounds__(256) k_fb_lap(const int64_t* __restrict__ n2e_ptr, const int32_t* __restrict__ n2e,
+                                                const double* __restrict__ h, int64_t nn, double* __restrict__ node)
+{
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= nn) return;
+    const int64_t j0 = n2e_ptr[n], j1 = n2e_ptr[n + 1];
+    const double c = (double)(j1 - j0);
+    for (int i = 0; i < 3; ++i) {
+        double sxx = 0.0, syy = 0.0;
+        for (int64_t j = j0; j < j1; ++j) {
+            sxx += h[6 * (int64_t)(n2e[j] / 3) + 2 * i];
+            syy += h[6 * (int64_t)(n2e[j] / 3) + 2 * i + 1];
+        }
+        node[n * NODE_STRIDE + NF_LAP + i] = j1 > j0 ? sxx / c + syy / c : 0.0;
+    }
+}
+
+// =====================================================================================
 // launchers
 // =====================================================================================
 static inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) / nt); }
@@ -1452,6 +1540,16 @@ void launch_ctl_finish(int64_t* meta, const int32_t* off, int64_t ne, const unsi
                        ProbParams* prm, int32_t n_problems, hipStream_t s)
 {
     hipLaunchKernelGGL(k_ctl_finish, dim3(1), dim3(64), 0, s, meta, off, ne, rep, cap, prm, n_problems);
+}
+void launch_feedback(const double* stats, double* node, ElemGeo* geo, const int64_t* n2e_ptr, const int32_t* n2e,
+                     int64_t nn, int64_t ne, double alpha, int32_t rey, double* gn, double* h, hipStream_t s)
+{
+    if (nn <= 0 || ne <= 0) return;
+    hipLaunchKernelGGL(k_fb_nodes, dim3(blocks_for(nn, 256)), dim3(256), 0, s, stats, node, nn, alpha, rey);
+    hipLaunchKernelGGL(k_fb_grad, dim3(blocks_for(ne, 256)), dim3(256), 0, s, geo, (const double*)node, ne);
+    hipLaunchKernelGGL(k_fb_gn, dim3(blocks_for(nn, 256)), dim3(256), 0, s, (const ElemGeo*)geo, n2e_ptr, n2e, nn, gn);
+    hipLaunchKernelGGL(k_fb_h, dim3(blocks_for(ne, 256)), dim3(256), 0, s, (const ElemGeo*)geo, (const double*)gn, ne, h);
+    hipLaunchKernelGGL(k_fb_lap, dim3(blocks_for(nn, 256)), dim3(256), 0, s, n2e_ptr, n2e, (const double*)h, nn, node);
 }
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s)
 {

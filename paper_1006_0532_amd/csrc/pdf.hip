@@ -178,6 +178,16 @@ pdf_status regroup_any(pdf_ens_s* E, bool mix, bool counts_ready, bool advance_s
                                      : regroup<double>(E, mix, counts_ready, advance_step, s);
 }
 
+// statistics of the last pass -> nodal fields and their derived fields (FP64 records; the
+// FP32 copy of the mixed form follows)
+void apply_feedback(pdf_ens_s* E, hipStream_t s)
+{
+    DevGrid& g = E->dg;
+    launch_feedback(E->stats, g.node, g.geo, g.n2e_ptr, g.n2e, g.nn, g.ne, E->fb_alpha, E->fb_rey, E->fb_gn,
+                    E->fb_h, s);
+    if (g.node32) launch_f64_to_f32(g.node, g.node32, g.nn * NODE_STRIDE, s);
+}
+
 // one time step: particle loop, then grouping, binning, mixing and statistics
 template <class R>
 pdf_status step_once(pdf_ens_s* E, hipStream_t s)
@@ -205,6 +215,7 @@ pdf_status step_once(pdf_ens_s* E, hipStream_t s)
     HIP_TRY(hipGetLastError());
     pdf_status st = regroup<R>(E, true, true, true, s);
     if (st != PDF_OK) return st;
+    if (E->fb_on) apply_feedback(E, s);
     E->step += 1;
     return PDF_OK;
 }
@@ -355,6 +366,9 @@ void free_devgrid(DevGrid& g)
         dfree(g.node);
         dfree(g.n2e_ptr);
         dfree(g.n2e);
+    } else if (g.own_fields) {
+        dfree(g.geo);
+        dfree(g.node);
     }
     dfree(g.node32);
     g = DevGrid{};
@@ -622,6 +636,8 @@ pdf_status pdf_ens_destroy(pdf_ens E)
     dfree(E->gu3); dfree(E->ctl_clone); dfree(E->ctl_off); dfree(E->ctl_rep); dfree(E->big_list);
     dfree(E->big_count); dfree(E->d_prm); dfree(E->d_scalar);
     free_devgrid(E->dg);
+    dfree(E->fb_gn);
+    dfree(E->fb_h);
     delete E;
     return PDF_OK;
 }
@@ -1104,6 +1120,49 @@ pdf_status pdf_timing(pdf_ens E, int32_t enable, double* ms_out, int64_t* launch
     }
     E->timing = enable != 0;
     return PDF_OK;
+}
+
+pdf_status pdf_set_feedback(pdf_ens E, int32_t enable, double alpha, int32_t feed_rey, void* hip_stream)
+{
+    if (!E || !std::isfinite(alpha)) {
+        set_error("pdf_set_feedback: invalid argument");
+        return PDF_E_INVAL;
+    }
+    HIP_TRY(hipSetDevice(E->grid->device));
+    hipStream_t s = as_stream(hip_stream);
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    drop_graphs(E);
+    E->stream = s;
+    E->fb_on = enable != 0;
+    E->fb_alpha = alpha;
+    E->fb_rey = feed_rey != 0;
+    if (!enable) return PDF_OK;
+    DevGrid& g = E->dg;
+    if (!g.owned && !g.own_fields) {
+        // the grid's records are shared with other ensembles: feed back into copies
+        ElemGeo* geo = nullptr;
+        double* node = nullptr;
+        pdf_status st = dalloc(&geo, g.ne);
+        if (st == PDF_OK) st = dalloc(&node, g.nn * NODE_STRIDE);
+        if (st != PDF_OK) {
+            dfree(geo);
+            return st;
+        }
+        HIP_TRY(hipMemcpyAsync(geo, g.geo, sizeof(ElemGeo) * g.ne, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(node, g.node, sizeof(double) * g.nn * NODE_STRIDE, hipMemcpyDeviceToDevice, s));
+        g.geo = geo;
+        g.node = node;
+        g.own_fields = true;
+    }
+    if (!E->fb_gn) {
+        pdf_status st = dalloc(&E->fb_gn, 6 * g.nn);
+        if (st == PDF_OK) st = dalloc(&E->fb_h, 6 * g.ne);
+        if (st != PDF_OK) return st;
+    }
+    apply_feedback(E, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return check_device_error(E);
 }
 
 pdf_status pdf_get_options(pdf_ens E, pdf_options* out)

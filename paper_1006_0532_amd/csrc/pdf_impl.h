@@ -123,6 +123,7 @@ struct DevGrid {
     int64_t* n2e_ptr = nullptr;
     int32_t* n2e = nullptr;
     bool owned = false;              // arrays allocated by the ensemble
+    bool own_fields = false;         // geo and node copied for statistics feedback (one problem)
 };
 
 struct pdf_ens_s {
@@ -170,6 +171,12 @@ struct pdf_ens_s {
     int lds_max = 0;            // particles per element on chip in the workgroup kernel
     int ppl = 4;                // particles per lane in the wavefront kernel
     int adv_block = 256;        // threads per workgroup of the particle loop
+    // statistics feedback after every step
+    bool fb_on = false;
+    double fb_alpha = 1.0;
+    int32_t fb_rey = 0;
+    double* fb_gn = nullptr;    // [nn][6]
+    double* fb_h = nullptr;     // [ne][6]
     // graph-captured steps
     bool use_graph = false;
     bool capturing = false;    // a step is being captured into a graph

@@ -27,7 +27,8 @@ STATUS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "HIP", -4: "MESH", -5: "CAPACIT
 # every symbol include/pdf.h declares
 EXPORTS = ["pdf_grid_create", "pdf_grid_destroy", "pdf_particles_init", "pdf_ens_destroy", "pdf_step",
            "pdf_stats", "pdf_control", "pdf_count", "pdf_particles_export", "pdf_particles_import",
-           "pdf_counters", "pdf_timing", "pdf_get_options", "pdf_set_options", "pdf_autotune", "pdf_sync",
+           "pdf_counters", "pdf_timing", "pdf_set_feedback", "pdf_get_options", "pdf_set_options", "pdf_autotune",
+           "pdf_sync",
            "pdf_last_error"]
 PDF_FP64, PDF_MIXED = 0, 1
 
@@ -94,6 +95,7 @@ def load(path: str = LIB_PATH):
                                  C.c_uint64, vp],
         "pdf_counters": [vp, C.c_int32, i64p],
         "pdf_timing": [vp, C.c_int32, dp, i64p],
+        "pdf_set_feedback": [vp, C.c_int32, C.c_double, C.c_int32, vp],
         "pdf_get_options": [vp, C.POINTER(Options)],
         "pdf_set_options": [vp, C.POINTER(Options)],
         "pdf_autotune": [vp, dp, C.c_int32, vp, C.POINTER(Options), ip, dp],
@@ -263,6 +265,11 @@ class Ensemble:
         cnt = (C.c_int64 * PDF_NTIMERS)()
         _check(load().pdf_timing(self.h, int(enable), ms, cnt))
         return {TIMER_NAMES[i]: (ms[i], cnt[i]) for i in range(PDF_NTIMERS)}
+
+    def set_feedback(self, enable: bool = True, alpha: float = 1.0, feed_rey: bool = False):
+        """Feed the nodal statistics back into the fields now and after every step."""
+        _check(load().pdf_set_feedback(self.h, int(bool(enable)), float(alpha), int(bool(feed_rey)),
+                                       C.c_void_p(self.stream)))
 
     def options(self) -> dict:
         o = Options()

@@ -259,3 +259,20 @@ def test_autotune_changes_no_result(gpu):
         assert np.array_equal(sa[k], sb[k]), k
     np.testing.assert_allclose(a.stats(), b.stats(), rtol=1e-12, atol=1e-15)
     assert a.options()["adv_block"] in (128, 256)
+
+
+def test_mixed_with_statistics_feedback(gpu):
+    """Mixed form with the fed-back mean and Reynolds stresses against the FP64 oracle."""
+    _say("test_mixed_with_statistics_feedback")
+    mesh, f, mo, ini = W.redistribution_test(ppe=60)
+    og = O.Grid(mesh, f, mo)
+    oe = O.Ensemble(og, ini)
+    gg = gpu.Grid(mesh, f, mo)
+    ge = gpu.Ensemble(gg, ini, precision=gpu.PDF_MIXED)
+    oe.feedback(0.5, True)
+    ge.set_feedback(True, 0.5, True)
+    for n in range(10):
+        oe.step(0.01)
+        ge.step(0.01)
+        oe.feedback(0.5, True)
+    _check_mixed_stats(ge.stats(), oe.stats(), "step 10")

@@ -292,3 +292,49 @@ def test_cavity_small_parity(gpu):
     c = ge.counters()
     assert c["wall_a"] > 0 and c["reflections"] > 0 and c["source_hits"] > 0
     assert c == oe.counters()
+
+
+@pytest.mark.parametrize("feed_rey", [False, True])
+def test_statistics_feedback_parity(gpu, feed_rey):
+    """Redistribution test of Sec. 3.7: the fed-back mean (alpha = 0.5) and optionally the
+    fed-back Reynolds stresses drive the next step; number control every step."""
+    _say(f"test_statistics_feedback_parity feed_rey={feed_rey}")
+    mesh, f, mo, ini = W.redistribution_test(ppe=60)
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    oe.feedback(0.5, feed_rey)
+    ge.set_feedback(True, 0.5, feed_rey)
+    excl = set()
+    for n in range(8):
+        oe.step(0.01)
+        ge.step(0.01)
+        ro, rg = oe.control(10, 100), ge.control(10, 100)
+        assert ro == {k: rg[k] for k in ro}, (ro, rg)
+        oe.feedback(0.5, feed_rey)
+        rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+    compare_stats(ge.stats(), oe.stats(), _skip_nodes(mesh, excl))
+    assert len(excl) <= 4
+
+
+def test_feedback_in_graph_replay_is_bitwise_eager(gpu):
+    _say("test_feedback_in_graph_replay_is_bitwise_eager")
+    mesh, f, mo, ini = W.redistribution_test(nx=10, ny=12, ppe=60)
+    gg = gpu.Grid(mesh, f, mo)
+    a, b = gpu.Ensemble(gg, ini), gpu.Ensemble(gg, ini)
+    for e in (a, b):
+        e.set_feedback(True, 0.5, True)
+    b.set_options(use_graph=1)
+    for chunk in (2, 3, 4):
+        a.step(0.01, chunk)
+        b.step(0.01, chunk)
+        sa, sb = a.export(), b.export()
+        for k in sa:
+            assert np.array_equal(sa[k], sb[k]), (chunk, k)
+        assert np.array_equal(a.stats(), b.stats(), equal_nan=True)
+    # the grid itself is untouched: a fresh ensemble without feedback equals the oracle's set-up
+    c = gpu.Ensemble(gg, ini)
+    og = O.Grid(mesh, f, mo)
+    oc = O.Ensemble(og, ini)
+    c.step(0.01)
+    oc.step(0.01)
+    compare_states(c.export(), oc.export(), og.export()["frame"], _length(mesh))
