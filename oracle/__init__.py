@@ -83,6 +83,7 @@ def lib():
         "orc_stats": (C.c_int32, [P, dp]),
         "orc_refresh_stats": (C.c_int32, [P]),
         "orc_feedback": (C.c_int32, [P, C.c_double, C.c_int32]),
+        "orc_cfl_dt": (C.c_double, [P, C.c_double]),
         "orc_control": (C.c_int32, [P, C.c_int32, C.c_int32, i64p]),
         "orc_counters": (None, [P, i64p]),
         "orc_bin_element": (C.c_int32, [C.c_int32, dp, u64p, ip, C.c_int32, ip, ip]),
@@ -265,6 +266,10 @@ class Ensemble:
         rc = lib().orc_feedback(self.h, float(alpha), int(bool(feed_rey)))
         if rc != 0:
             raise RuntimeError(f"orc_feedback: {rc}")
+
+    def cfl_dt(self, cfl: float = 0.7) -> float:
+        """Time step of Eq. (26) from the last statistics."""
+        return float(lib().orc_cfl_dt(self.h, float(cfl)))
 
     def refresh_stats(self):
         lib().orc_refresh_stats(self.h)

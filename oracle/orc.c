@@ -1156,3 +1156,31 @@ int32_t orc_feedback(orc_ens* E, double alpha, int32_t feed_rey)
     derive_fields(g);
     return 0;
 }
+
+/* Time step of Eq. (26): CFL * min_n sqrt(A_n) / max_n ||<Z>_n||_2, A_n the average area
+   of the elements around node n, <Z>_n = (<U_1>, <U_2>, <U_3>, <omega>, <psi>) the nodal
+   means of the last statistics (nodes without particles are skipped).  Returns 0 when no
+   node has a positive mean norm. */
+double orc_cfl_dt(const orc_ens* E, double cfl)
+{
+    if (!E->have_stats) return -1.0;
+    const orc_grid* g = E->g;
+    double lmin = INFINITY, zmax = 0.0;
+    for (int64_t n = 0; n < g->nn; ++n) {
+        const int64_t c = g->n2e_ptr[n + 1] - g->n2e_ptr[n];
+        if (c > 0) {
+            double a = 0.0;
+            for (int64_t j = g->n2e_ptr[n]; j < g->n2e_ptr[n + 1]; ++j) a += g->area[g->n2e[j]];
+            const double l = sqrt(a / (double)c);
+            if (l < lmin) lmin = l;
+        }
+        const double* o = E->stats + n * NSTAT;
+        if (o[0] > 0.0) {
+            double z = 0.0;
+            for (int q = 1; q <= 5; ++q) z += o[q] * o[q];
+            z = sqrt(z);
+            if (z > zmax) zmax = z;
+        }
+    }
+    return zmax > 0.0 ? cfl * lmin / zmax : 0.0;
+}
