@@ -238,6 +238,12 @@ pdf_status pdf_timing(pdf_ens ens, int32_t enable, double* ms_out, int64_t* laun
  * enable = 0 stops the feedback and keeps the current fields.  Synchronises. */
 pdf_status pdf_set_feedback(pdf_ens ens, int32_t enable, double alpha, int32_t feed_rey, void* hip_stream);
 
+/* Time step of Eq. (26) (Sec. 3.1) for one problem from its last statistics:
+ * *dt_out = cfl * min_n sqrt(A_n) / max_n ||(<U_1>, <U_2>, <U_3>, <omega>, <psi>)_n||_2, A_n the
+ * average area of the elements around node n (the paper uses cfl = 0.7); nodes without
+ * particles do not enter the maximum; 0 when no node has a positive norm.  Synchronises. */
+pdf_status pdf_cfl_dt(pdf_ens ens, int32_t problem, double cfl, double* dt_out, void* hip_stream);
+
 /* Launch options of an ensemble; none changes any result.
  *  use_graph  1: pdf_step replays every two steps from a captured HIP graph on a
  *             stream of the ensemble (ordered after and before hip_stream by events),

@@ -134,6 +134,10 @@ void launch_ctl_finish(int64_t* meta, const int32_t* off, int64_t ne, const unsi
 // then element gradients and nodal Laplacians of <U>; gn [6 nn] and h [6 ne] are scratch
 void launch_feedback(const double* stats, double* node, ElemGeo* geo, const int64_t* n2e_ptr, const int32_t* n2e,
                      int64_t nn, int64_t ne, double alpha, int32_t rey, double* gn, double* h, hipStream_t s);
+// Eq. (26) ingredients over nodes [n0, n0 + nn): out[0] = min sqrt(A_n), out[1] = max |<Z>_n|
+// as double bits; out must hold +inf and 0 on entry
+void launch_cfl(const ElemGeo* geo, const int64_t* n2e_ptr, const int32_t* n2e, const double* stats, int64_t n0,
+                int64_t nn, unsigned long long* out, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 void launch_f64_to_f32(const double* in, float* out, int64_t n, hipStream_t s);

@@ -1436,6 +1436,40 @@ __global__ void __launch_bounds__(256) k_fb_lap(const int64_t* __restrict__ n2e_
     }
 }
 
+// time step of Eq. (26): min over nodes of sqrt(average element area around the node) and
+// max over nodes with particles of |(<U>, <omega>, <psi>)|, as the bits of non-negative
+// doubles (their integer order is their numeric order)
+__global__ void __launch_bounds__(256) k_cfl(const ElemGeo* __restrict__ geo, const int64_t* __restrict__ n2e_ptr,
+                                             const int32_t* __restrict__ n2e, const double* __restrict__ stats,
+                                             int64_t n0, int64_t nn, unsigned long long* __restrict__ out)
+{
+    const int64_t n = n0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double l = __builtin_inf(), z = 0.0;
+    if (n < n0 + nn) {
+        const int64_t j0 = n2e_ptr[n], j1 = n2e_ptr[n + 1];
+        if (j1 > j0) {
+            double a = 0.0;
+            for (int64_t j = j0; j < j1; ++j) a += geo[n2e[j] / 3].area;
+            l = sqrt(a / (double)(j1 - j0));
+        }
+        const double* o = stats + n * NSTAT;
+        if (o[0] > 0.0) {
+            double s = 0.0;
+            for (int q = 1; q <= 5; ++q) s += o[q] * o[q];
+            z = sqrt(s);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        l = fmin(l, __shfl_xor(l, o));
+        z = fmax(z, __shfl_xor(z, o));
+    }
+    if (lane_id() == 0) {
+        atomicMin(out, (unsigned long long)__double_as_longlong(l));
+        atomicMax(out + 1, (unsigned long long)__double_as_longlong(z));
+    }
+}
+
 // =====================================================================================
 // launchers
 // =====================================================================================
@@ -1550,6 +1584,11 @@ void launch_feedback(const double* stats, double* node, ElemGeo* geo, const int6
     hipLaunchKernelGGL(k_fb_gn, dim3(blocks_for(nn, 256)), dim3(256), 0, s, (const ElemGeo*)geo, n2e_ptr, n2e, nn, gn);
     hipLaunchKernelGGL(k_fb_h, dim3(blocks_for(ne, 256)), dim3(256), 0, s, (const ElemGeo*)geo, (const double*)gn, ne, h);
     hipLaunchKernelGGL(k_fb_lap, dim3(blocks_for(nn, 256)), dim3(256), 0, s, n2e_ptr, n2e, (const double*)h, nn, node);
+}
+void launch_cfl(const ElemGeo* geo, const int64_t* n2e_ptr, const int32_t* n2e, const double* stats, int64_t n0,
+                int64_t nn, unsigned long long* out, hipStream_t s)
+{
+    if (nn > 0) hipLaunchKernelGGL(k_cfl, dim3(blocks_for(nn, 256)), dim3(256), 0, s, geo, n2e_ptr, n2e, stats, n0, nn, out);
 }
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s)
 {

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -1162,6 +1163,32 @@ pdf_status pdf_set_feedback(pdf_ens E, int32_t enable, double alpha, int32_t fee
     apply_feedback(E, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
+    return check_device_error(E);
+}
+
+pdf_status pdf_cfl_dt(pdf_ens E, int32_t problem, double cfl, double* dt_out, void* hip_stream)
+{
+    if (!E || !dt_out || problem < 0 || problem >= E->n_problems || !(cfl > 0.0) || !std::isfinite(cfl)) {
+        set_error("pdf_cfl_dt: invalid argument");
+        return PDF_E_INVAL;
+    }
+    HIP_TRY(hipSetDevice(E->grid->device));
+    hipStream_t s = as_stream(hip_stream);
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    const ProbParams& P = E->h_prm[problem];
+    const DevGrid& g = E->dg;
+    union { double d; unsigned long long u; } inf_bits;
+    inf_bits.d = std::numeric_limits<double>::infinity();
+    launch_fill_u64(E->d_scalar, 1, inf_bits.u, s);
+    launch_fill_u64(E->d_scalar + 1, 1, 0ull, s);
+    launch_cfl(g.geo, g.n2e_ptr, g.n2e, E->stats, P.noff, P.nn, E->d_scalar, s);
+    unsigned long long r[2];
+    HIP_TRY(hipMemcpyAsync(r, E->d_scalar, sizeof(r), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double lmin, zmax;
+    std::memcpy(&lmin, &r[0], sizeof(double));
+    std::memcpy(&zmax, &r[1], sizeof(double));
+    *dt_out = zmax > 0.0 ? cfl * lmin / zmax : 0.0;
     return check_device_error(E);
 }
 

@@ -27,7 +27,7 @@ STATUS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "HIP", -4: "MESH", -5: "CAPACIT
 # every symbol include/pdf.h declares
 EXPORTS = ["pdf_grid_create", "pdf_grid_destroy", "pdf_particles_init", "pdf_ens_destroy", "pdf_step",
            "pdf_stats", "pdf_control", "pdf_count", "pdf_particles_export", "pdf_particles_import",
-           "pdf_counters", "pdf_timing", "pdf_set_feedback", "pdf_get_options", "pdf_set_options", "pdf_autotune",
+           "pdf_counters", "pdf_timing", "pdf_set_feedback", "pdf_cfl_dt", "pdf_get_options", "pdf_set_options", "pdf_autotune",
            "pdf_sync",
            "pdf_last_error"]
 PDF_FP64, PDF_MIXED = 0, 1
@@ -96,6 +96,7 @@ def load(path: str = LIB_PATH):
         "pdf_counters": [vp, C.c_int32, i64p],
         "pdf_timing": [vp, C.c_int32, dp, i64p],
         "pdf_set_feedback": [vp, C.c_int32, C.c_double, C.c_int32, vp],
+        "pdf_cfl_dt": [vp, C.c_int32, C.c_double, dp, vp],
         "pdf_get_options": [vp, C.POINTER(Options)],
         "pdf_set_options": [vp, C.POINTER(Options)],
         "pdf_autotune": [vp, dp, C.c_int32, vp, C.POINTER(Options), ip, dp],
@@ -270,6 +271,12 @@ class Ensemble:
         """Feed the nodal statistics back into the fields now and after every step."""
         _check(load().pdf_set_feedback(self.h, int(bool(enable)), float(alpha), int(bool(feed_rey)),
                                        C.c_void_p(self.stream)))
+
+    def cfl_dt(self, cfl: float = 0.7, problem: int = 0) -> float:
+        """Time step of Eq. (26) from the last statistics."""
+        v = C.c_double()
+        _check(load().pdf_cfl_dt(self.h, int(problem), float(cfl), C.byref(v), C.c_void_p(self.stream)))
+        return float(v.value)
 
     def options(self) -> dict:
         o = Options()

@@ -338,3 +338,30 @@ def test_feedback_in_graph_replay_is_bitwise_eager(gpu):
     c.step(0.01)
     oc.step(0.01)
     compare_states(c.export(), oc.export(), og.export()["frame"], _length(mesh))
+
+
+def test_cfl_time_step(gpu):
+    """Eq. (26) from the GPU statistics: equal to the oracle's on the channel after some
+    steps, and per problem in a batched ensemble."""
+    _say("test_cfl_time_step")
+    mesh, f, mo, ini = W.channel_small(nx=20, ny=24)
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    for n in range(3):
+        oe.step(1e-3)
+        ge.step(1e-3)
+    a, b = ge.cfl_dt(0.7), oe.cfl_dt(0.7)
+    assert b > 0 and abs(a - b) <= 1e-12 * b, (a, b)
+    m2 = box(6, 6, length=2.0)
+    f2 = W.uniform_fields(m2, mean_u=(0.5, 0.2, 0.0), mean_omega=2.0)
+    g2 = gpu.Grid(m2, f2, mo)
+    ini2 = W.init_desc(ppe=30, bins=(2, 2, 1), src_x=1.0, src_r=0.3, seed=77)
+    bat = gpu.Ensemble([gg, g2], [ini, ini2])
+    bat.step([1e-3, 2e-3], 2)
+    for p, (m, ff, d, dt) in enumerate(((mesh, f, ini, 1e-3), (m2, f2, ini2, 2e-3))):
+        dd = dict(d)
+        dd["seed"] = int(d["seed"]) ^ (p << 32)
+        o = O.Ensemble(O.Grid(m, ff, mo), dd)
+        o.step(dt)
+        o.step(dt)
+        a, b = bat.cfl_dt(0.7, problem=p), o.cfl_dt(0.7)
+        assert abs(a - b) <= 1e-12 * b, (p, a, b)
