@@ -812,10 +812,13 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// wavefronts per workgroup of the wavefront element kernel (LDS stays within 64 KiB)
+// wavefronts per workgroup of the wavefront element kernel (LDS stays within 64 KiB), and
+// the wavefronts per SIMD the register budget is set for (up to five particles per lane
+// fit 128 registers: four wavefronts per SIMD, as the LDS of four workgroups per CU allows)
 template <int PPL>
 struct WaveBlock {
     static constexpr int waves = PPL >= 6 ? 2 : 4;
+    static constexpr int per_simd = PPL <= 5 ? 4 : 1;
 };
 
 // One wavefront per element (up to 64*PPL particles, PPL per lane).  Lanes own particles
@@ -826,12 +829,15 @@ struct WaveBlock {
 // (n_below = -1 for the first tier, so empty elements are handled there); the last tier
 // puts larger elements on the workgroup kernel's worklist (last != 0).
 template <int PPL, class R>
-__global__ void __launch_bounds__(256) k_element_wave(ElementArgs<R> a, int n_below, int last)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WaveBlock<PPL>::per_simd)))
+k_element_wave(ElementArgs<R> a, int n_below, int last)
 {
     constexpr int N = 64 * PPL;
     constexpr int RED = (13 * 65 * 8 + 15) & ~15;         // transposed reduction, padded rows
-    constexpr int R1 = (24 * N > RED) ? 24 * N : RED;     // keys / (w psi, w) / reduction
-    constexpr int WAVE_BYTES = R1 + 4 * N + 8 * N;
+    // keys, pids, 31-bit keys, claims [24N] / then (w psi, w) pairs [16N] and bin means (at
+    // most n bins) [8N] / then the transposed reduction
+    constexpr int R1 = (24 * N > RED) ? 24 * N : RED;
+    constexpr int WAVE_BYTES = R1 + 4 * N;
     static_assert(WAVE_BYTES % 16 == 0 && R1 % 16 == 0, "16-byte aligned LDS slices");
     constexpr int WPB = WaveBlock<PPL>::waves;
     __shared__ __attribute__((aligned(16))) unsigned char sm[WPB * WAVE_BYTES];
@@ -842,11 +848,12 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs<R> a, int n_be
     unsigned char* base = sm + wave * WAVE_BYTES;
     uint64_t* kk = reinterpret_cast<uint64_t*>(base);          // [N] keys by position
     uint64_t* kpid = kk + N;                                     // [N] pids by position
-    uint64_t* claim = kpid + N;                                  // [N] rank collision check
+    uint32_t* k32 = reinterpret_cast<uint32_t*>(kpid + N);       // [N] 31-bit keys by position
+    uint32_t* claim = k32 + N;                                   // [N] rank collision check
     R* wacc = reinterpret_cast<R*>(base);
     R* red = reinterpret_cast<R*>(base);
     int32_t* ord = reinterpret_cast<int32_t*>(base + R1);
-    R* bmean = reinterpret_cast<R*>(base + R1 + 4 * N);
+    R* bmean = reinterpret_cast<R*>(base + 16 * N);
     const int64_t s0 = __builtin_amdgcn_readfirstlane(a.start[e]);
     const int n = __builtin_amdgcn_readfirstlane(a.start[e + 1]) - (int)s0;
     if (n <= n_below) return;   // an earlier tier's element
@@ -890,6 +897,7 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs<R> a, int n_be
     for (int l = 0; l < 3; ++l) {
         uint64_t mk[PPL];
         int lo[PPL], hi[PPL];
+        uint64_t kmin = ~0ull, kmax = 0ull;
 #pragma unroll
         for (int r = 0; r < PPL; ++r) {
             mk[r] = order_bits(l == 0 ? U0[r] : (l == 1 ? U1[r] : U2[r]));
@@ -897,52 +905,73 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs<R> a, int n_be
             lo[r] = div_small(t * n + (int)C - 1, (int)C);
             hi[r] = div_small((t + 1) * n + (int)C - 1, (int)C);
             if (lane + 64 * r < n) {
-                kk[pos[r]] = mk[r];
-                kpid[pos[r]] = pd[r];
+                kmin = mk[r] < kmin ? mk[r] : kmin;
+                kmax = mk[r] > kmax ? mk[r] : kmax;
             }
         }
-        // pad the keys to a multiple of 8 with the largest key (never below a real key)
+        // 31-bit keys: (key - min) shifted right until the element's span fits; the map is
+        // monotone, so ranks by these keys are exact unless two keys fall together, which
+        // the slot claim below detects
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint64_t a = __shfl_xor(kmin, o), b = __shfl_xor(kmax, o);
+            kmin = a < kmin ? a : kmin;
+            kmax = b > kmax ? b : kmax;
+        }
+        const uint64_t span = kmax - kmin;
+        const int sh = (span >> 31) ? 33 - __clzll(span) : 0;
+        uint32_t m32[PPL];
+#pragma unroll
+        for (int r = 0; r < PPL; ++r) {
+            m32[r] = (uint32_t)((mk[r] - kmin) >> sh);
+            if (lane + 64 * r < n) {
+                kk[pos[r]] = mk[r];
+                kpid[pos[r]] = pd[r];
+                k32[pos[r]] = m32[r];
+            }
+        }
+        // pad to a multiple of 8 with the largest 31-bit key (never below a real key)
         const int n8 = (n + 7) & ~7;
-        for (int q = n + lane; q < n8; q += 64) kk[q] = ~0ull;
+        for (int q = n + lane; q < n8; q += 64) k32[q] = 0x7FFFFFFFu;
         wave_sync();
-        // rank inside the group by the velocity key alone (ties are rare); eight keys per
-        // iteration so that one LDS round trip serves eight comparisons per particle
+        // rank inside the group by the 31-bit key: a < b is the sign of a - b (both below
+        // 2^31), so the comparisons are independent integer operations
+        auto lt = [](uint32_t a, uint32_t b) { return (int)((a - b) >> 31); };
         int rk[PPL];
 #pragma unroll
         for (int r = 0; r < PPL; ++r) rk[r] = 0;
         if (l == 0) {
             for (int q = 0; q < n8; q += 8) {
-                const ulonglong2 k01 = *reinterpret_cast<const ulonglong2*>(kk + q);
-                const ulonglong2 k23 = *reinterpret_cast<const ulonglong2*>(kk + q + 2);
-                const ulonglong2 k45 = *reinterpret_cast<const ulonglong2*>(kk + q + 4);
-                const ulonglong2 k67 = *reinterpret_cast<const ulonglong2*>(kk + q + 6);
+                const uint4 ka = *reinterpret_cast<const uint4*>(k32 + q);
+                const uint4 kb = *reinterpret_cast<const uint4*>(k32 + q + 4);
 #pragma unroll
                 for (int r = 0; r < PPL; ++r)
-                    rk[r] += (k01.x < mk[r]) + (k01.y < mk[r]) + (k23.x < mk[r]) + (k23.y < mk[r]) +
-                             (k45.x < mk[r]) + (k45.y < mk[r]) + (k67.x < mk[r]) + (k67.y < mk[r]);
+                    rk[r] += lt(ka.x, m32[r]) + lt(ka.y, m32[r]) + lt(ka.z, m32[r]) + lt(ka.w, m32[r]) +
+                             lt(kb.x, m32[r]) + lt(kb.y, m32[r]) + lt(kb.z, m32[r]) + lt(kb.w, m32[r]);
             }
         } else {
 #pragma unroll
             for (int r = 0; r < PPL; ++r)
                 if (lane + 64 * r < n) {
                     int q = lo[r];
-                    for (; q + 4 <= hi[r]; q += 4) {
-                        const uint64_t k0 = kk[q], k1 = kk[q + 1], k2 = kk[q + 2], k3 = kk[q + 3];
-                        rk[r] += (k0 < mk[r]) + (k1 < mk[r]) + (k2 < mk[r]) + (k3 < mk[r]);
-                    }
-                    for (; q < hi[r]; ++q) rk[r] += kk[q] < mk[r] ? 1 : 0;
+                    for (; q + 4 <= hi[r]; q += 4)
+                        rk[r] += lt(k32[q], m32[r]) + lt(k32[q + 1], m32[r]) + lt(k32[q + 2], m32[r]) +
+                                 lt(k32[q + 3], m32[r]);
+                    for (; q < hi[r]; ++q) rk[r] += lt(k32[q], m32[r]);
                 }
         }
         // equal keys give equal ranks: detect by claiming the slots, then rank exactly
         // by (key, pid) in that case
 #pragma unroll
         for (int r = 0; r < PPL; ++r)
-            if (lane + 64 * r < n) claim[lo[r] + (rk[r] < hi[r] - lo[r] ? rk[r] : hi[r] - lo[r] - 1)] = pd[r];
+            if (lane + 64 * r < n)
+                claim[lo[r] + (rk[r] < hi[r] - lo[r] ? rk[r] : hi[r] - lo[r] - 1)] = (uint32_t)(lane + 64 * r);
         wave_sync();
         bool clash = false;
 #pragma unroll
         for (int r = 0; r < PPL; ++r)
-            if (lane + 64 * r < n) clash |= claim[lo[r] + (rk[r] < hi[r] - lo[r] ? rk[r] : hi[r] - lo[r] - 1)] != pd[r];
+            if (lane + 64 * r < n)
+                clash |= claim[lo[r] + (rk[r] < hi[r] - lo[r] ? rk[r] : hi[r] - lo[r] - 1)] != (uint32_t)(lane + 64 * r);
         if (__ballot(clash)) {
 #pragma unroll
             for (int r = 0; r < PPL; ++r) {
@@ -983,6 +1012,7 @@ __global__ void __launch_bounds__(256) k_element_wave(ElementArgs<R> a, int n_be
         }
     }
     wave_sync();
+    // bin means of psi, weighted (App. A)
     for (int b = lane; b < Cp; b += 64) {
         const int lo = div_small(b * n + Cp - 1, Cp), hi = div_small((b + 1) * n + Cp - 1, Cp);
         Acc<R> sw, swp;
