@@ -212,8 +212,10 @@ __device__ __forceinline__ void area_coords(const ElemGeo* __restrict__ G, doubl
 {
     const double xa = G->x[0], xb = G->x[1], xc = G->x[2];
     const double ya = G->y[0], yb = G->y[1], yc = G->y[2];
-    na = 0.5 * ((xc - xb) * (y - yb) - (yc - yb) * (x - xb));
-    nc = 0.5 * ((x - xb) * (ya - yb) - (y - yb) * (xa - xb));
+    // explicit fused multiply-adds: the same rounding in every kernel, whatever registers
+    // (scalar or vector) the vertex coordinates sit in
+    na = 0.5 * fma(xc - xb, y - yb, -((yc - yb) * (x - xb)));
+    nc = 0.5 * fma(x - xb, ya - yb, -((y - yb) * (xa - xb)));
     nb = G->area - na - nc;
 }
 

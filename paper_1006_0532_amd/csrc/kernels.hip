@@ -72,31 +72,54 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
     const R om = a.s.om[i];
     const uint64_t pid = a.s.pid[i];
 
-    // (a1) P1 interpolation of the nodal fields (Eq. 37); area coordinates in FP64
-    double na, nb, nc;
-    area_coords(G, x0, y0, na, nb, nc);
-    const double ia = 1.0 / G->area;
-    const R la = (R)(na * ia), lb = (R)(nb * ia), lc = (R)(nc * ia);
-    const R* __restrict__ FA = a.node + (int64_t)G->node[0] * NODE_STRIDE;
-    const R* __restrict__ FB = a.node + (int64_t)G->node[1] * NODE_STRIDE;
-    const R* __restrict__ FC = a.node + (int64_t)G->node[2] * NODE_STRIDE;
-    // interpolation in three groups of fields; the empty asm statements keep the
-    // compiler from hoisting all 63 node loads at once (register pressure)
-    auto ip = [&](int q) { return la * FA[q] + lb * FB[q] + lc * FC[q]; };
-    const R gu0 = (R)G->gu[0], gu1 = (R)G->gu[1], gu2 = (R)G->gu[2], gu3 = (R)G->gu[3], gu4 = (R)G->gu[4],
-            gu5 = (R)G->gu[5];
+    // (a1) P1 interpolation of the nodal fields (Eq. 37); area coordinates in FP64.
+    // The lanes of a wavefront mostly share one or two elements (particles are in
+    // canonical order): loop over the distinct elements, so that element and node records
+    // are wave-uniform scalar loads instead of per-lane vector loads.
+    R f[21], gu[6];
+    {
+        unsigned long long todo = __ballot(true);
+        while (todo) {
+            const int src = __ffsll((long long)todo) - 1;
+            const int32_t eu = __builtin_amdgcn_readfirstlane(__shfl(e, src));
+            todo &= ~__ballot(e == eu);
+            if (e == eu) {
+                const ElemGeo* Gu = a.geo + eu;
+                double na, nb, nc;
+                area_coords(Gu, x0, y0, na, nb, nc);
+                const double ia = 1.0 / Gu->area;
+                const R la = (R)(na * ia), lb = (R)(nb * ia), lc = (R)(nc * ia);
+                const R* __restrict__ FA = a.node + (int64_t)Gu->node[0] * NODE_STRIDE;
+                const R* __restrict__ FB = a.node + (int64_t)Gu->node[1] * NODE_STRIDE;
+                const R* __restrict__ FC = a.node + (int64_t)Gu->node[2] * NODE_STRIDE;
+                // three groups of fields; the empty asm statements keep the compiler from
+                // loading all 63 node values at once.  Explicit fused multiply-adds fix the
+                // rounding whatever the operands' registers.
+                auto ip = [&](int q) { return fma(lc, FC[q], fma(lb, FB[q], la * FA[q])); };
+#pragma unroll
+                for (int q = 0; q < 7; ++q) f[q] = ip(q);
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int q = 7; q < 14; ++q) f[q] = ip(q);
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int q = 14; q < 21; ++q) f[q] = ip(q);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) gu[q] = (R)Gu->gu[q];
+            }
+        }
+    }
+    const R gu0 = gu[0], gu1 = gu[1], gu2 = gu[2], gu3 = gu[3], gu4 = gu[4], gu5 = gu[5];
 
     // (a2) closure (Eqs. 11, 18, 20)
-    const R R11 = ip(NF_RE), R22 = ip(NF_RE + 1), R33 = ip(NF_RE + 2);
-    const R R12 = ip(NF_RE + 3), R13 = ip(NF_RE + 4), R23 = ip(NF_RE + 5);
-    const R Om = ip(NF_OM);
-    asm volatile("" ::: "memory");
+    const R R11 = f[NF_RE], R22 = f[NF_RE + 1], R33 = f[NF_RE + 2];
+    const R R12 = f[NF_RE + 3], R13 = f[NF_RE + 4], R23 = f[NF_RE + 5];
+    const R Om = f[NF_OM];
     const R k = R(0.5) * (R11 + R22 + R33);
     const R eps = Om * (k + nu * CT * CT * Om);
     const R prod = -(R11 * gu0 + R12 * gu1 + R12 * gu2 + R22 * gu3 + R13 * gu4 + R23 * gu5);
-    const R W11 = ip(NF_WP), W22 = ip(NF_WP + 1), W33 = ip(NF_WP + 2);
-    const R W12 = ip(NF_WP + 3), W13 = ip(NF_WP + 4), W23 = ip(NF_WP + 5);
-    asm volatile("" ::: "memory");
+    const R W11 = f[NF_WP], W22 = f[NF_WP + 1], W33 = f[NF_WP + 2];
+    const R W12 = f[NF_WP + 3], W13 = f[NF_WP + 4], W23 = f[NF_WP + 5];
     const R wpR = W11 * R11 + W22 * R22 + W33 * R33 + R(2) * (W12 * R12 + W13 * R13 + W23 * R23);
     R c0eps = -R(2) * wpR / (R(3) * k);
     if (c0eps < R(0)) {
@@ -107,16 +130,6 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
     const R ik = R(1) / k;
     const R G11 = (W11 - R(0.5) * eps) * ik, G22 = (W22 - R(0.5) * eps) * ik, G33 = (W33 - R(0.5) * eps) * ik;
     const R G12 = W12 * ik, G13 = W13 * ik, G23 = W23 * ik;
-    R f[21];
-    f[NF_MU] = ip(NF_MU);
-    f[NF_MU + 1] = ip(NF_MU + 1);
-    f[NF_MU + 2] = ip(NF_MU + 2);
-    f[NF_GP] = ip(NF_GP);
-    f[NF_GP + 1] = ip(NF_GP + 1);
-    f[NF_LAP] = ip(NF_LAP);
-    f[NF_LAP + 1] = ip(NF_LAP + 1);
-    f[NF_LAP + 2] = ip(NF_LAP + 2);
-    asm volatile("" ::: "memory");
 
     // random numbers: 6 Gaussians and one uniform (Sec. 3.9)
     const Words4 wA = rng_draw(P.key, pid, step, TAG_STEP, 0);
