@@ -22,6 +22,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP64 vector issue of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one FP64 lane
+# operation per lane and cycle; the 78.6 TFLOP/s figure counts a fused multiply-add twice)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# algorithmic VALU lane operations per particle of the particle loop (interpolation,
+# closure, 2 Philox blocks, 3 Box-Muller pairs, Eqs. 27, 19, 7, one tracking test)
+VALU_OPS_PER_PARTICLE = {"advance": 1000}
 
 # algorithmic HBM bytes per live particle (FP64 state): what each kernel must read and
 # write once
@@ -274,21 +280,36 @@ def main():
     psteps = float(sum(live))
     value = psteps / elapsed
 
-    # dominant kernel and its roofline (bytes per launch = bytes per particle x live)
+    # rooflines (bytes or operations per launch = per-particle figure x live particles);
+    # the particle loop is bound by FP64 vector issue, the others by HBM
     kern = {k: v for k, v in tim.items() if v[1] > 0}
-    dom = max(kern, key=lambda k: kern[k][0])
     mean_live = psteps / args.steps
-    roof = None
-    if dom in BYTES_PER_PARTICLE:
-        avg_ms = kern[dom][0] / kern[dom][1]
-        achieved = BYTES_PER_PARTICLE[dom] * mean_live / (avg_ms * 1e-3) / 1e9
-        default = (args.nx, args.ny, args.ppe) == (400, 500, 200)
-        traffic = counter_traffic(dom, default)
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else round(traffic / 1e9, 3),
-                "traffic_unit": "GB per launch",
-                "avg_ms": round(avg_ms, 4), "bytes_per_particle": BYTES_PER_PARTICLE[dom]}
+    default = (args.nx, args.ny, args.ppe) == (400, 500, 200)
+
+    def roofline(name):
+        if name not in kern or (name not in BYTES_PER_PARTICLE and name not in VALU_OPS_PER_PARTICLE):
+            return None
+        avg_ms = kern[name][0] / kern[name][1]
+        traffic = counter_traffic(name, default)
+        r = {"kernel": name, "avg_ms": round(avg_ms, 4),
+             "traffic": None if traffic is None else round(traffic / 1e9, 3), "traffic_unit": "GB per launch"}
+        if name in VALU_OPS_PER_PARTICLE:
+            ach = VALU_OPS_PER_PARTICLE[name] * mean_live / (avg_ms * 1e-3) / 1e12
+            r.update(bound="alu", achieved=round(ach, 2), peak=round(VALU_PEAK_TOPS, 2),
+                     unit="T FP64 lane-ops/s", frac=round(ach / VALU_PEAK_TOPS, 4),
+                     ops_per_particle=VALU_OPS_PER_PARTICLE[name])
+            hbm = BYTES_PER_PARTICLE[name] * mean_live / (avg_ms * 1e-3) / 1e9
+            r["hbm_GBs"] = round(hbm, 1)
+            r["hbm_frac"] = round(hbm / HBM_PEAK_GBS, 4)
+        else:
+            ach = BYTES_PER_PARTICLE[name] * mean_live / (avg_ms * 1e-3) / 1e9
+            r.update(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                     frac=round(ach / HBM_PEAK_GBS, 4), bytes_per_particle=BYTES_PER_PARTICLE[name])
+        return r
+
+    dom = max(kern, key=lambda k: kern[k][0])
+    roof = roofline(dom)
+    rooflines = [r for r in (roofline(k) for k in ("advance", "element_pass", "scatter")) if r]
     per_kernel = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches": v[1]} for k, v in kern.items()}
     for k, bpp in BYTES_PER_PARTICLE.items():
         if k in kern:
@@ -322,7 +343,8 @@ def main():
         "config": {"workload": "channel_large", "triangles": mesh.n_elems, "nodes": mesh.n_nodes,
                    "particles": n0, "ppe": args.ppe, "dt": dt, "control": list(ctl),
                    "bins": [4, 2, 2], "precision": "fp64", "parallelism": "single GPU"},
-        "roofline": roof, "per_kernel": per_kernel, "cpu_baseline": cpu, "forms": forms,
+        "roofline": roof, "rooflines": rooflines, "per_kernel": per_kernel, "cpu_baseline": cpu,
+        "forms": forms,
     }
     print(json.dumps(out), flush=True)
 
