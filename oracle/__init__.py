@@ -43,7 +43,8 @@ class InitDesc(C.Structure):
     _fields_ = [("ppe", C.c_int32), ("u_sigma", C.c_double), ("omega_shape", C.c_double),
                 ("src_x", C.c_double), ("src_y", C.c_double), ("src_r", C.c_double),
                 ("src_continuous", C.c_int32), ("bins", C.c_int32 * 3),
-                ("min_per_bin", C.c_int32), ("seed", C.c_uint64), ("problem", C.c_int32)]
+                ("min_per_bin", C.c_int32), ("seed", C.c_uint64), ("problem", C.c_int32),
+                ("estimator", C.c_int32)]
 
 
 _lib = None
@@ -205,6 +206,7 @@ def make_init(d: dict, problem: int = 0) -> InitDesc:
     for i in range(3):
         s.bins[i] = int(d["bins"][i])
     s.min_per_bin = int(d["min_per_bin"]); s.seed = int(d["seed"]); s.problem = int(problem)
+    s.estimator = int(d.get("estimator", 0))
     return s
 
 

@@ -572,12 +572,24 @@ static int walk(const orc_grid* g, int32_t* pe, double* px, double* py, double* 
  * ===================================================================================== */
 typedef struct { int64_t c[8]; } counters;
 
+/* Weights of the three nodal values that give a field at (x, y) in element e: the area
+   coordinates (P1 interpolation, Eq. 37), or 1/3 each when the statistics are used as
+   element averages of the nodal values (Sec. 3.3, second estimator). */
+static void field_weights(const orc_ens* E, int32_t e, double x, double y, double lam[3])
+{
+    if (E->d.estimator == 1) {
+        lam[0] = lam[1] = lam[2] = 1.0 / 3.0;
+        return;
+    }
+    orc_bary(E->g, e, x, y, lam);
+}
+
 static int advance_one(const orc_ens* E, part* p, double dt, counters* cn)
 {
     const orc_grid* g = E->g;
     const orc_model* m = &g->m;
     double lam[3], f[NF];
-    orc_bary(g, p->e, p->x, p->y, lam);
+    field_weights(E, p->e, p->x, p->y, lam);
     interp(g, p->e, lam, f);
     const double* gu = g->gU + 6 * (int64_t)p->e;
     const double R11 = f[F_RE], R22 = f[F_RE + 1], R33 = f[F_RE + 2];
@@ -658,7 +670,7 @@ static int advance_one(const orc_ens* E, part* p, double dt, counters* cn)
     }
     if (hit) {
         double lam2[3], f2[NF];
-        orc_bary(g, e, xn, yn, lam2);
+        field_weights(E, e, xn, yn, lam2);
         interp(g, e, lam2, f2);
         un[0] = un[1] = un[2] = 0.0;
         omn = orc_gamma(1.0 / m->C4, f2[F_OM], E->d.seed, E->d.problem, p->pid, (uint32_t)E->step, TAG_WALL_GAMMA);
@@ -832,10 +844,64 @@ static void element_pass(orc_ens* E, double dt, int mix)
  * node (Eq. 37) over the particles of the elements around the node; second moments
  * about the node's own mean with the same weights (Eq. 36).
  * ===================================================================================== */
+/* Second estimator of Sec. 3.3 (Eqs. 35-36): means and central second moments of the
+   particles of every element (first pass), then at every node the plain average over the
+   surrounding elements that hold particles (second pass).  W is the total weight of the
+   surrounding elements; a node without such elements gets NaN. */
+static void compute_stats_elements(orc_ens* E)
+{
+    const orc_grid* g = E->g;
+    double* es = (double*)malloc(sizeof(double) * NSTAT * g->ne);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t e = 0; e < g->ne; ++e) {
+        double W = 0.0, M[5] = { 0, 0, 0, 0, 0 }, C[7] = { 0, 0, 0, 0, 0, 0, 0 };
+        for (int64_t r = E->seg[e]; r < E->seg[e + 1]; ++r) {
+            const part* P = &E->p[E->order[r]];
+            W += P->w;
+            M[0] += P->w * P->u[0]; M[1] += P->w * P->u[1]; M[2] += P->w * P->u[2];
+            M[3] += P->w * P->om; M[4] += P->w * P->psi;
+        }
+        if (W > 0.0) for (int q = 0; q < 5; ++q) M[q] /= W;
+        for (int64_t r = E->seg[e]; r < E->seg[e + 1]; ++r) {
+            const part* P = &E->p[E->order[r]];
+            double d[5] = { P->u[0] - M[0], P->u[1] - M[1], P->u[2] - M[2], P->om - M[3], P->psi - M[4] };
+            C[0] += P->w * d[0] * d[0]; C[1] += P->w * d[1] * d[1]; C[2] += P->w * d[2] * d[2];
+            C[3] += P->w * d[0] * d[1]; C[4] += P->w * d[0] * d[2]; C[5] += P->w * d[1] * d[2];
+            C[6] += P->w * d[4] * d[4];
+        }
+        double* o = es + e * NSTAT;
+        o[0] = W;
+        for (int q = 0; q < 5; ++q) o[1 + q] = M[q];
+        for (int q = 0; q < 7; ++q) o[6 + q] = W > 0.0 ? C[q] / W : 0.0;
+    }
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t nd = 0; nd < g->nn; ++nd) {
+        double* o = E->stats + nd * NSTAT;
+        double W = 0.0, S[NSTAT] = { 0 };
+        int K = 0;
+        for (int64_t j = g->n2e_ptr[nd]; j < g->n2e_ptr[nd + 1]; ++j) {
+            const double* x = es + (int64_t)g->n2e[j] * NSTAT;
+            W += x[0];
+            if (x[0] > 0.0) {
+                ++K;
+                for (int q = 1; q < NSTAT; ++q) S[q] += x[q];
+            }
+        }
+        o[0] = W;
+        for (int q = 1; q < NSTAT; ++q) o[q] = K > 0 ? S[q] / (double)K : NAN;
+    }
+    free(es);
+    E->have_stats = 1;
+}
+
 static void compute_stats(orc_ens* E)
 {
     const orc_grid* g = E->g;
     if (!E->stats) E->stats = (double*)malloc(sizeof(double) * NSTAT * g->nn);
+    if (E->d.estimator == 1) {
+        compute_stats_elements(E);
+        return;
+    }
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t nd = 0; nd < g->nn; ++nd) {
         double W = 0.0, S[5] = { 0, 0, 0, 0, 0 };
@@ -897,7 +963,8 @@ static int grow(orc_ens* E, int64_t need)
 orc_ens* orc_init(orc_grid* g, const orc_init_desc* d, char* err, int32_t errlen)
 {
     if (!g || !d || d->ppe < 0 || d->min_per_bin < 1 || d->bins[0] < 1 || d->bins[1] < 1 || d->bins[2] < 1 ||
-        !(d->omega_shape >= 1.0) || !(d->u_sigma >= 0.0) || !(d->src_r >= 0.0)) {
+        !(d->omega_shape >= 1.0) || !(d->u_sigma >= 0.0) || !(d->src_r >= 0.0) || d->estimator < 0 ||
+        d->estimator > 1) {
         seterr(err, errlen, "bad init descriptor");
         return NULL;
     }
@@ -926,7 +993,7 @@ orc_ens* orc_init(orc_grid* g, const orc_init_desc* d, char* err, int32_t errlen
             P->y = yA + a * (yB - yA) + b * (yC - yA);
             P->e = (int32_t)e;
             double lam[3], f[NF];
-            orc_bary(g, (int32_t)e, P->x, P->y, lam);
+            field_weights(E, (int32_t)e, P->x, P->y, lam);
             interp(g, (int32_t)e, lam, f);
             double z01[2], z23[2];
             orc_box_muller(w[2], w[3], z01);

@@ -32,6 +32,8 @@ typedef struct {
     double src_x, src_y, src_r; int32_t src_continuous;
     int32_t bins[3]; int32_t min_per_bin;
     uint64_t seed; int32_t problem;
+    int32_t estimator;   /* 0: P1-weighted nodal moments and P1 interpolation;
+                            1: element means averaged to the nodes, element-averaged fields (Sec. 3.3) */
 } orc_init_desc;
 
 /* --- units (used by the pins) --- */
