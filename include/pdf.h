@@ -68,6 +68,14 @@ typedef int32_t pdf_status;
 /* state precision of an ensemble (pdf_init_desc.precision) */
 enum { PDF_FP64 = 0, PDF_MIXED = 1 };
 
+/* estimator of the Eulerian statistics (pdf_init_desc.estimator), Sec. 3.3:
+ *  PDF_EST_P1       nodal moments weighted by the P1 shape functions of the particles'
+ *                   positions; fields interpolated to the particles (Eq. 37);
+ *  PDF_EST_ELEMENT  the paper's two passes: element means and central moments, averaged over
+ *                   the surrounding elements with particles; a particle uses the average of
+ *                   its element's three nodal values. */
+enum { PDF_EST_P1 = 0, PDF_EST_ELEMENT = 1 };
+
 /* boundary kinds of element edges; edge k of a triangle is the edge opposite vertex k */
 enum { PDF_EDGE_INTERIOR = 0, PDF_EDGE_WALL = 1, PDF_EDGE_SLIP = 2, PDF_EDGE_PERIODIC = 3 };
 
@@ -128,7 +136,8 @@ typedef struct {
  *  seed           seed of the counter-based generator (key: seed low word, seed high
  *                 word XOR the problem's index in the ensemble);
  *  capacity       particle slots for this problem (0: max(2 x ppe x n_elems, 1024));
- *                 the ensemble allocates the sum over its problems. */
+ *                 the ensemble allocates the sum over its problems;
+ *  estimator      PDF_EST_P1 or PDF_EST_ELEMENT (the same for every problem). */
 typedef struct {
     int32_t ppe;
     double u_sigma, omega_shape;
@@ -139,6 +148,7 @@ typedef struct {
     int32_t precision;
     uint64_t seed;
     int64_t capacity;
+    int32_t estimator;
 } pdf_init_desc;
 
 /* Result of pdf_control. */

@@ -69,6 +69,8 @@ struct NodeArgs {
     int64_t* meta;
     int32_t* big_count;     // [2] large-element worklist, no-slip resample list
     int32_t advance_step;   // 1 after a time step: the device step counter moves on
+    int32_t estimator;      // 1: element means and moments averaged over the elements around
+                            //    the node (then part holds W, sums and shift per element)
 };
 
 template <class R>

@@ -88,7 +88,11 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
                 double na, nb, nc;
                 area_coords(Gu, x0, y0, na, nb, nc);
                 const double ia = 1.0 / Gu->area;
-                const R la = (R)(na * ia), lb = (R)(nb * ia), lc = (R)(nc * ia);
+                // statistics as element averages of the nodal values (second estimator of
+                // Sec. 3.3) or P1 interpolation (Eq. 37)
+                const bool avg = P.estimator == 1;
+                const R la = avg ? R(1) / R(3) : (R)(na * ia), lb = avg ? R(1) / R(3) : (R)(nb * ia),
+                        lc = avg ? R(1) / R(3) : (R)(nc * ia);
                 const R* __restrict__ FA = a.node + (int64_t)Gu->node[0] * NODE_STRIDE;
                 const R* __restrict__ FB = a.node + (int64_t)Gu->node[1] * NODE_STRIDE;
                 const R* __restrict__ FC = a.node + (int64_t)Gu->node[2] * NODE_STRIDE;
@@ -258,8 +262,10 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
         const R* __restrict__ HA = a.node + (int64_t)C->node[0] * NODE_STRIDE;
         const R* __restrict__ HB = a.node + (int64_t)C->node[1] * NODE_STRIDE;
         const R* __restrict__ HC = a.node + (int64_t)C->node[2] * NODE_STRIDE;
-        const R omw = (R)(pa_ / C->area) * HA[NF_OM] + (R)(pb_ / C->area) * HB[NF_OM] +
-                      (R)(pc_ / C->area) * HC[NF_OM];
+        const bool avg = P.estimator == 1;
+        const R omw = avg ? (HA[NF_OM] + HB[NF_OM] + HC[NF_OM]) / R(3)
+                          : (R)(pa_ / C->area) * HA[NF_OM] + (R)(pb_ / C->area) * HB[NF_OM] +
+                                (R)(pc_ / C->area) * HC[NF_OM];
         v0 = v1 = v2 = R(0);
         // Eq. (58): omega ~ Gamma with this mean, drawn by k_wall_resample (the sampler is
         // kept out of the particle loop, whose register budget it would set)
@@ -720,6 +726,7 @@ __device__ __forceinline__ void element_body(const ElementArgs<R>& a, int32_t e,
     // IECM (Eq. 24); statistics partials; canonical write-out
     const R fmix = (R)mix_fraction(a.mix, P.dt, a.tm[e]);
     const double inv_area = G->inv_area;
+    const bool est = P.estimator == 1;
     R rs[3][5];
 #pragma unroll
     for (int v = 0; v < 3; ++v)
@@ -748,7 +755,9 @@ __device__ __forceinline__ void element_body(const ElementArgs<R>& a, int32_t e,
         a.out.elem[o] = e;
         double na, nb, nc;
         area_coords(G, x, y, na, nb, nc);
-        const R lam[3] = {(R)(na * inv_area), (R)(nb * inv_area), (R)(nc * inv_area)};
+        // second estimator: the element's own sums (weight 1 on the first vertex slot)
+        const R lam[3] = {est ? R(1) : (R)(na * inv_area), est ? R(0) : (R)(nb * inv_area),
+                          est ? R(0) : (R)(nc * inv_area)};
         add_partials<R>(acc, rs, lam, w, u0, u1, u2, om, psi);
     }
     // fixed-order reduction: butterfly inside each wavefront, then waves in order
@@ -764,7 +773,10 @@ __device__ __forceinline__ void element_body(const ElementArgs<R>& a, int32_t e,
     if (tid < 3 * NPART) {
         Acc<R> s;
         for (int w = 0; w < NT / 64; ++w) s.add(red[w * 3 * NPART + tid]);
-        a.part[(int64_t)e * 3 * NPART + tid] = s.value();
+        R v = s.value();
+        // second estimator: the second slot carries the shift of the element's sums
+        if (est && tid >= NPART && tid < NPART + 5) v = a.shift[(int64_t)G->node[0] * 5 + (tid - NPART)];
+        a.part[(int64_t)e * 3 * NPART + tid] = v;
     }
 }
 
@@ -1039,6 +1051,7 @@ k_element_wave(ElementArgs<R> a, int n_below, int last)
 
     const R fmix = (R)mix_fraction(a.mix, P.dt, a.tm[e]);
     const double inv_area = G->inv_area;
+    const bool est = P.estimator == 1;
     R rs[3][5];
 #pragma unroll
     for (int v = 0; v < 3; ++v)
@@ -1070,7 +1083,9 @@ k_element_wave(ElementArgs<R> a, int n_below, int last)
         a.out.elem[o] = (int32_t)e;
         double na, nb, nc;
         area_coords(G, x, y, na, nb, nc);
-        const R lam[3] = {(R)(na * inv_area), (R)(nb * inv_area), (R)(nc * inv_area)};
+        // second estimator: the element's own sums (weight 1 on the first vertex slot)
+        const R lam[3] = {est ? R(1) : (R)(na * inv_area), est ? R(0) : (R)(nb * inv_area),
+                          est ? R(0) : (R)(nc * inv_area)};
         add_partials<R>(acc, rs, lam, w, u0, u1, u2, om, psi);
     }
     // fixed-order wavefront reduction through LDS: row q holds the 64 lanes' values
@@ -1082,7 +1097,10 @@ k_element_wave(ElementArgs<R> a, int n_below, int last)
         if (lane < NPART) {
             Acc<R> s;
             for (int l = 0; l < 64; ++l) s.add(red[lane * 65 + l]);
-            a.part[e * 3 * NPART + v * NPART + lane] = s.value();
+            R val = s.value();
+            // second estimator: the second slot carries the shift of the element's sums
+            if (est && v == 1 && lane < 5) val = a.shift[(int64_t)G->node[0] * 5 + lane];
+            a.part[e * 3 * NPART + v * NPART + lane] = val;
         }
         wave_sync();
     }
@@ -1103,6 +1121,45 @@ __global__ void __launch_bounds__(256) k_node_finalize(NodeArgs<R> a)
         a.big_count[1] = 0;          // list of no-slip resamples, empty for the next step
     }
     if (i >= a.nn) return;
+    if (a.estimator == 1) {
+        // second estimator of Sec. 3.3: plain average over the surrounding elements with
+        // particles of the element means (shift + sum / W) and central moments
+        double W = 0.0, Sm[5] = {0, 0, 0, 0, 0}, Sc[7] = {0, 0, 0, 0, 0, 0, 0};
+        int K = 0;
+        for (int64_t j = a.n2e_ptr[i]; j < a.n2e_ptr[i + 1]; ++j) {
+            const R* pp = a.part + (int64_t)(a.n2e[j] / 3) * 3 * NPART;
+            const double We = (double)pp[0];
+            W += We;
+            if (!(We > 0.0)) continue;
+            ++K;
+            double d[5];
+            for (int q = 0; q < 5; ++q) {
+                d[q] = (double)pp[1 + q] / We;
+                Sm[q] += (double)pp[NPART + q] + d[q];
+            }
+            Sc[0] += (double)pp[6] / We - d[0] * d[0];
+            Sc[1] += (double)pp[7] / We - d[1] * d[1];
+            Sc[2] += (double)pp[8] / We - d[2] * d[2];
+            Sc[3] += (double)pp[9] / We - d[0] * d[1];
+            Sc[4] += (double)pp[10] / We - d[0] * d[2];
+            Sc[5] += (double)pp[11] / We - d[1] * d[2];
+            Sc[6] += (double)pp[12] / We - d[4] * d[4];
+        }
+        double* o = a.stats + i * NSTAT;
+        R* r = a.shift + i * 5;
+        o[0] = W;
+        if (K == 0) {
+            const double nan = __builtin_nan("");
+            for (int q = 1; q < NSTAT; ++q) o[q] = nan;
+            return;
+        }
+        for (int q = 0; q < 5; ++q) {
+            o[1 + q] = Sm[q] / (double)K;
+            r[q] = (R)o[1 + q];
+        }
+        for (int q = 0; q < 7; ++q) o[6 + q] = Sc[q] / (double)K;
+        return;
+    }
     Acc<R> S[NPART];
     for (int64_t j = a.n2e_ptr[i]; j < a.n2e_ptr[i + 1]; ++j) {
         const R* pp = a.part + (int64_t)a.n2e[j] * NPART;
@@ -1169,7 +1226,9 @@ __global__ void __launch_bounds__(256) k_init(InitArgs<R> a)
     const double y = G->y[0] + s * (G->y[1] - G->y[0]) + t * (G->y[2] - G->y[0]);
     double na, nb, nc;
     area_coords(G, x, y, na, nb, nc);
-    const R la = (R)(na * G->inv_area), lb = (R)(nb * G->inv_area), lc = (R)(nc * G->inv_area);
+    const bool avg = P.estimator == 1;
+    const R la = avg ? R(1) / R(3) : (R)(na * G->inv_area), lb = avg ? R(1) / R(3) : (R)(nb * G->inv_area),
+            lc = avg ? R(1) / R(3) : (R)(nc * G->inv_area);
     const R* FA = a.node + (int64_t)G->node[0] * NODE_STRIDE;
     const R* FB = a.node + (int64_t)G->node[1] * NODE_STRIDE;
     const R* FC = a.node + (int64_t)G->node[2] * NODE_STRIDE;

@@ -164,6 +164,7 @@ pdf_status regroup(pdf_ens_s* E, bool mix, bool counts_ready, bool advance_step,
     na.meta = E->d_meta;
     na.big_count = E->big_count;
     na.advance_step = advance_step ? 1 : 0;
+    na.estimator = E->h_prm[0].estimator;
     {
         Timed t(E, T_NODE, s);
         launch_node_finalize<R>(na, s);
@@ -664,9 +665,10 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
             !(d.omega_shape >= 1.0) || !(d.u_sigma >= 0.0) || !(d.src_r >= 0.0) || !std::isfinite(d.u_sigma) ||
             !std::isfinite(d.omega_shape) || !std::isfinite(d.src_x) || !std::isfinite(d.src_y) ||
             !std::isfinite(d.src_r) || (d.precision != PDF_FP64 && d.precision != PDF_MIXED) ||
-            d.precision != descs[0].precision || d.capacity < 0 || g->device != grids[0]->device) {
+            d.precision != descs[0].precision || d.capacity < 0 || g->device != grids[0]->device ||
+            (d.estimator != PDF_EST_P1 && d.estimator != PDF_EST_ELEMENT) || d.estimator != descs[0].estimator) {
             set_error("pdf_particles_init: invalid descriptor (bins product <= 1024, omega_shape >= 1, one "
-                      "precision and one device for all problems)");
+                      "precision, estimator and device for all problems)");
             return PDF_E_INVAL;
         }
         const int64_t n0p = g->ne * (int64_t)d.ppe;
@@ -721,6 +723,7 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
             P.bins2 = d.bins[2];
             P.minpb = d.min_per_bin;
             P.ppe = d.ppe > 0 ? d.ppe : 1;
+            P.estimator = d.estimator;
             P.eoff = eo;
             P.ne = g->ne;
             P.noff = no;

@@ -88,6 +88,7 @@ struct ProbParams {
     int32_t src_cont;
     int32_t bins0, bins1, bins2, minpb;
     int32_t ppe;
+    int32_t estimator;             // 0: P1-weighted moments, P1 fields; 1: element means to nodes
     int64_t eoff, ne;              // element range in the ensemble
     int64_t noff, nn;              // node range
     int64_t soff;                  // first set-up slot

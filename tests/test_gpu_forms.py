@@ -281,3 +281,17 @@ def test_mixed_with_statistics_feedback(gpu):
         ge.step(0.01)
         oe.feedback(0.5, True)
     _check_mixed_stats(ge.stats(), oe.stats(), "step 10")
+
+
+def test_mixed_element_estimator(gpu):
+    _say("test_mixed_element_estimator")
+    mesh, f, mo, ini = W.channel_small()
+    ini = dict(ini, estimator=1)
+    og = O.Grid(mesh, f, mo)
+    oe = O.Ensemble(og, ini)
+    gg = gpu.Grid(mesh, f, mo)
+    ge = gpu.Ensemble(gg, ini, precision=gpu.PDF_MIXED)
+    for n in range(10):
+        oe.step(1e-3)
+        ge.step(1e-3)
+    _check_mixed_stats(ge.stats(), oe.stats(), "step 10")

@@ -365,3 +365,28 @@ def test_cfl_time_step(gpu):
         o.step(dt)
         a, b = bat.cfl_dt(0.7, problem=p), o.cfl_dt(0.7)
         assert abs(a - b) <= 1e-12 * b, (p, a, b)
+
+
+def test_element_estimator_parity(gpu):
+    """Second estimator of Sec. 3.3 (element means averaged to the nodes, element-averaged
+    fields), with number control and statistics feedback."""
+    _say("test_element_estimator_parity")
+    mesh = W.channel_mesh(20, 24, stretch=1.1 ** 8, seed=21)
+    f = W.channel_fields(mesh)
+    mo = W.model_constants()
+    ini = W.init_desc(ppe=40, bins=(4, 2, 2), src_x=3.0, src_r=0.4, estimator=1)
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    compare_stats(ge.stats(), oe.stats())
+    ge.set_feedback(True, 1.0, False)
+    oe.feedback(1.0, False)
+    excl = set()
+    for n in range(6):
+        oe.step(2e-3)
+        ge.step(2e-3)
+        ro, rg = oe.control(38, 42), ge.control(38, 42)
+        assert ro == {k: rg[k] for k in ro}, (ro, rg)
+        oe.feedback(1.0, False)
+        rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+    compare_stats(ge.stats(), oe.stats(), _skip_nodes(mesh, excl))
+    assert ge.cfl_dt(0.7) == pytest.approx(oe.cfl_dt(0.7), rel=1e-12)
