@@ -85,6 +85,7 @@ def lib():
         "orc_refresh_stats": (C.c_int32, [P]),
         "orc_feedback": (C.c_int32, [P, C.c_double, C.c_int32]),
         "orc_cfl_dt": (C.c_double, [P, C.c_double]),
+        "orc_redistribute": (C.c_int64, [P, C.c_int32]),
         "orc_control": (C.c_int32, [P, C.c_int32, C.c_int32, i64p]),
         "orc_counters": (None, [P, i64p]),
         "orc_bin_element": (C.c_int32, [C.c_int32, dp, u64p, ip, C.c_int32, ip, ip]),
@@ -268,6 +269,13 @@ class Ensemble:
         rc = lib().orc_feedback(self.h, float(alpha), int(bool(feed_rey)))
         if rc != 0:
             raise RuntimeError(f"orc_feedback: {rc}")
+
+    def redistribute(self, n_min: int) -> int:
+        """App. B redistribution; returns the number of moves."""
+        rc = lib().orc_redistribute(self.h, int(n_min))
+        if rc < 0:
+            raise RuntimeError(f"orc_redistribute: {rc}")
+        return int(rc)
 
     def cfl_dt(self, cfl: float = 0.7) -> float:
         """Time step of Eq. (26) from the last statistics."""

@@ -1251,3 +1251,85 @@ double orc_cfl_dt(const orc_ens* E, double cfl)
     }
     return zmax > 0.0 ? cfl * lmin / zmax : 0.0;
 }
+
+/* Particle redistribution (App. B): while the element holding the fewest particles (mine)
+   has fewer than n_min, one particle of the element holding the most (maxe) moves to mine.
+   Readings:
+   - ties in the fewest / most counts go to the lowest element index;
+   - the loop also stops once max - min <= 1 (a move would then only swap the two counts,
+     so the printed condition min != max would never end when the total does not divide
+     evenly);
+   - the particle that moves is drawn uniformly among maxe's current particles (canonical
+     order of the last pass, then later arrivals in arrival order); it keeps its pid and
+     weight, so the particle count and the total weight are unchanged;
+   - it takes position, velocity, frequency and scalar of a particle drawn uniformly among
+     mine's current particles (the copy of App. B); when mine is empty it keeps its own
+     properties and is placed at mine's centroid (in mine's frame, like every position
+     held by an element);
+   - move k draws one Philox block with key (seed, problem) and counter (k, step, tag 5):
+     word 0 picks the moving particle, word 1 the particle copied.
+   Returns the number of moves, or a negative status. */
+enum { TAG_REDIST = 5 };
+
+typedef struct { int64_t n, cap; int64_t* v; } ivec;
+static void ivec_push(ivec* a, int64_t x)
+{
+    if (a->n == a->cap) { a->cap = a->cap ? 2 * a->cap : 8; a->v = (int64_t*)realloc(a->v, sizeof(int64_t) * a->cap); }
+    a->v[a->n++] = x;
+}
+
+int64_t orc_redistribute(orc_ens* E, int32_t n_min)
+{
+    if (!E || n_min < 0) return ORC_E_INVAL;
+    if (!E->have_order) return ORC_E_STATE;
+    const orc_grid* g = E->g;
+    const int64_t ne = g->ne;
+    int64_t* cnt = (int64_t*)malloc(sizeof(int64_t) * ne);
+    ivec* cur = (ivec*)calloc(ne, sizeof(ivec));   /* current particles of the touched elements */
+    char* touched = (char*)calloc(ne, 1);
+    for (int64_t e = 0; e < ne; ++e) cnt[e] = E->seg[e + 1] - E->seg[e];
+    int64_t moves = 0;
+    for (;;) {
+        int64_t mine = 0, maxe = 0;
+        for (int64_t e = 1; e < ne; ++e) {
+            if (cnt[e] < cnt[mine]) mine = e;
+            if (cnt[e] > cnt[maxe]) maxe = e;
+        }
+        if (cnt[mine] >= n_min || cnt[maxe] - cnt[mine] <= 1) break;
+        for (int s = 0; s < 2; ++s) {
+            int64_t e = s ? maxe : mine;
+            if (!touched[e]) {
+                touched[e] = 1;
+                for (int64_t r = E->seg[e]; r < E->seg[e + 1]; ++r) ivec_push(&cur[e], E->order[r]);
+            }
+        }
+        uint32_t w[4];
+        draw4(E->d.seed, E->d.problem, (uint64_t)moves, (uint32_t)E->step, TAG_REDIST, 0, w);
+        int64_t r = (int64_t)(orc_u01(w[0]) * (double)cur[maxe].n);
+        part* P = &E->p[cur[maxe].v[r]];
+        int64_t moving = cur[maxe].v[r];
+        memmove(cur[maxe].v + r, cur[maxe].v + r + 1, sizeof(int64_t) * (cur[maxe].n - r - 1));
+        cur[maxe].n--;
+        if (cur[mine].n > 0) {
+            int64_t d = (int64_t)(orc_u01(w[1]) * (double)cur[mine].n);
+            const part* D = &E->p[cur[mine].v[d]];
+            P->x = D->x;
+            P->y = D->y;
+            P->u[0] = D->u[0]; P->u[1] = D->u[1]; P->u[2] = D->u[2];
+            P->om = D->om;
+            P->psi = D->psi;
+        } else {
+            P->x = (g->fx[3 * mine] + g->fx[3 * mine + 1] + g->fx[3 * mine + 2]) / 3.0;
+            P->y = (g->fy[3 * mine] + g->fy[3 * mine + 1] + g->fy[3 * mine + 2]) / 3.0;
+        }
+        P->e = (int32_t)mine;
+        ivec_push(&cur[mine], moving);
+        cnt[mine]++;
+        cnt[maxe]--;
+        ++moves;
+    }
+    if (moves > 0) E->have_order = 0;
+    for (int64_t e = 0; e < ne; ++e) free(cur[e].v);
+    free(cur); free(touched); free(cnt);
+    return moves;
+}

@@ -84,6 +84,8 @@ int32_t orc_refresh_stats(orc_ens*);
 int32_t orc_feedback(orc_ens*, double alpha, int32_t feed_rey);
 /* time step of Eq. (26) from the last statistics (see orc.c) */
 double orc_cfl_dt(const orc_ens*, double cfl);
+/* particle redistribution of App. B (see orc.c); returns the number of moves */
+int64_t orc_redistribute(orc_ens*, int32_t n_min);
 /* number control; report[0..5] = live, cloned, merged, empty elems, elems below, above */
 int32_t orc_control(orc_ens*, int32_t n_min, int32_t n_max, int64_t* report);
 /* counters: wall (a), wall (b), reflections, fallbacks, omega reflections, C0 clamps,
