@@ -248,6 +248,24 @@ pdf_status pdf_timing(pdf_ens ens, int32_t enable, double* ms_out, int64_t* laun
  * enable = 0 stops the feedback and keeps the current fields.  Synchronises. */
 pdf_status pdf_set_feedback(pdf_ens ens, int32_t enable, double alpha, int32_t feed_rey, void* hip_stream);
 
+/* Particle redistribution (App. B) of one problem (problem = -1: every problem, in order)
+ * on the canonical order of the last step: while the element with the fewest particles has
+ * fewer than n_min and at least two fewer than the element with the most, one particle of
+ * the fullest element moves to the emptiest (ties: lowest element index).  The moving
+ * particle is drawn uniformly among the giving element's current particles, keeps its
+ * pid and weight, and takes position, velocity, frequency and scalar of a particle drawn
+ * uniformly among the receiving element's current particles, or, when that element is
+ * empty, keeps its properties and sits at the element's centroid.  Move k of a problem
+ * draws one Philox block with the problem's key and counter (k, step, tag 5).  Particle
+ * count, pids and total weight do not change.  The moves are planned serially on the host
+ * from the element counts (one device-to-host copy of the segment starts) and applied by
+ * two device kernels; a later pdf_control needs another step first.  *moves_out (may be
+ * NULL) receives the number of moves.  Synchronises.
+ * Errors: PDF_E_INVAL (n_min < 0, bad problem), PDF_E_STATE (no step since the last
+ * control or redistribution), PDF_E_NOMEM, PDF_E_HIP. */
+pdf_status pdf_redistribute(pdf_ens ens, int32_t problem, int32_t n_min, int64_t* moves_out,
+                            void* hip_stream);
+
 /* Time step of Eq. (26) (Sec. 3.1) for one problem from its last statistics:
  * *dt_out = cfl * min_n sqrt(A_n) / max_n ||(<U_1>, <U_2>, <U_3>, <omega>, <psi>)_n||_2, A_n the
  * average area of the elements around node n (the paper uses cfl = 0.7); nodes without

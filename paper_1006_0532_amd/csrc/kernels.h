@@ -118,6 +118,12 @@ template <class R>
 void launch_ctl_apply(const ControlArgs<R>& a, hipStream_t s);
 template <class R>
 void launch_shift_init(const R* node, int64_t nn, R* shift, hipStream_t s);
+// redistribution moves (App. B): plan [m][4] = destination slot, position source (slot or
+// -(e + 1): centroid of element e), property source slot, new element; stage holds m
+// entries of scratch state
+template <class R>
+void launch_redistribute(const SoaT<R>& st, const SoaT<R>& stage, const int32_t* plan, const ElemGeo* geo, int64_t m,
+                         hipStream_t s);
 
 void launch_count(const int32_t* elem, const int64_t* nslots, int64_t n_ub, int64_t ne, int32_t* counts,
                   uint32_t* err, hipStream_t s);

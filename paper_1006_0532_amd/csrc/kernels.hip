@@ -1396,6 +1396,52 @@ __global__ void k_ctl_finish(int64_t* __restrict__ meta, const int32_t* __restri
         prm[p].next_pid += (uint64_t)(off[prm[p].eoff + prm[p].ne] - off[prm[p].eoff]);
 }
 
+// Particle redistribution (App. B), applied in two passes so that a slot that serves as a
+// copy source and also receives a new state is read before it is written.
+// plan[4 i ..]: destination slot, position source (slot, or -(e + 1) for the centroid of
+// element e), property source slot (velocity, frequency, scalar), new element.
+template <class R>
+__global__ void __launch_bounds__(256) k_redist_gather(SoaT<R> s, SoaT<R> stage, const int32_t* __restrict__ plan,
+                                                       const ElemGeo* __restrict__ geo, int64_t m)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int32_t xs = plan[4 * i + 1], ps = plan[4 * i + 2];
+    double x, y;
+    if (xs >= 0) {
+        x = s.x[xs];
+        y = s.y[xs];
+    } else {
+        const ElemGeo& G = geo[-(int64_t)xs - 1];
+        x = (G.x[0] + G.x[1] + G.x[2]) / 3.0;
+        y = (G.y[0] + G.y[1] + G.y[2]) / 3.0;
+    }
+    stage.x[i] = x;
+    stage.y[i] = y;
+    stage.u0[i] = s.u0[ps];
+    stage.u1[i] = s.u1[ps];
+    stage.u2[i] = s.u2[ps];
+    stage.om[i] = s.om[ps];
+    stage.psi[i] = s.psi[ps];
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_redist_write(SoaT<R> s, SoaT<R> stage, const int32_t* __restrict__ plan,
+                                                      int64_t m)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int32_t d = plan[4 * i];
+    s.x[d] = stage.x[i];
+    s.y[d] = stage.y[i];
+    s.u0[d] = stage.u0[i];
+    s.u1[d] = stage.u1[i];
+    s.u2[d] = stage.u2[i];
+    s.om[d] = stage.om[i];
+    s.psi[d] = stage.psi[i];
+    s.elem[d] = plan[4 * i + 3];
+}
+
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1692,6 +1738,15 @@ void launch_cfl(const ElemGeo* geo, const int64_t* n2e_ptr, const int32_t* n2e, 
 {
     if (nn > 0) hipLaunchKernelGGL(k_cfl, dim3(blocks_for(nn, 256)), dim3(256), 0, s, geo, n2e_ptr, n2e, stats, n0, nn, out);
 }
+template <class R>
+void launch_redistribute(const SoaT<R>& st, const SoaT<R>& stage, const int32_t* plan, const ElemGeo* geo, int64_t m,
+                         hipStream_t s)
+{
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_redist_gather<R>, dim3(blocks_for(m, 256)), dim3(256), 0, s, st, stage, plan, geo, m);
+    hipLaunchKernelGGL(k_redist_write<R>, dim3(blocks_for(m, 256)), dim3(256), 0, s, st, stage, plan, m);
+}
+
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s)
 {
     if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
@@ -1724,7 +1779,9 @@ void launch_shift_init(const R* node, int64_t nn, R* shift, hipStream_t s)
     template void launch_init<R>(const InitArgs<R>&, hipStream_t);                                       \
     template void launch_ctl_plan<R>(const ControlArgs<R>&, hipStream_t);                                \
     template void launch_ctl_apply<R>(const ControlArgs<R>&, hipStream_t);                               \
-    template void launch_shift_init<R>(const R*, int64_t, R*, hipStream_t);
+    template void launch_shift_init<R>(const R*, int64_t, R*, hipStream_t);                              \
+    template void launch_redistribute<R>(const SoaT<R>&, const SoaT<R>&, const int32_t*, const ElemGeo*, int64_t, \
+                                         hipStream_t);
 PDF_INSTANTIATE(double)
 PDF_INSTANTIATE(float)
 #undef PDF_INSTANTIATE

@@ -7,9 +7,12 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <set>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
+#include "device.h"
 #include "kernels.h"
 #include "pdf_impl.h"
 
@@ -547,6 +550,116 @@ pdf_status push_real(pdf_ens_s* E, void* dst, const std::vector<double>& in, hip
 
 }  // namespace
 
+
+// ---------------------------------------------------------------------------------------
+// Particle redistribution (App. B).  The moves are inherently serial (each one changes the
+// counts that select the next), so the host plans them from the element counts: an ordered
+// set of (count, element) finds the emptiest and the fullest element with ties to the
+// lowest index, and only the elements that take part keep explicit slot lists.  A slot
+// that moves several times, or copies a slot that moved before, is resolved to the
+// original slots its final position and properties come from, so that the device applies
+// all moves at once from the state of the last step.
+// ---------------------------------------------------------------------------------------
+namespace {
+
+constexpr uint32_t TAG_REDIST = 5;
+
+struct RedistSrc {
+    int32_t pos;    // slot whose position is taken, or -(e + 1): centroid of element e
+    int32_t prop;   // slot whose velocity, frequency and scalar are taken
+    int32_t elem;
+};
+
+int64_t plan_redistribution(const ProbParams& P, int32_t n_min, uint32_t step, const std::vector<int32_t>& start,
+                            std::unordered_map<int32_t, RedistSrc>& moved)
+{
+    const int64_t ne = P.ne, e0 = P.eoff;
+    std::vector<int64_t> cnt(ne);
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    for (int64_t e = 0; e < ne; ++e) {
+        cnt[e] = (int64_t)start[e0 + e + 1] - start[e0 + e];
+        lo = std::min(lo, cnt[e]);
+        hi = std::max(hi, cnt[e]);
+    }
+    if (ne == 0 || lo >= n_min || hi - lo <= 1) return 0;
+    std::set<std::pair<int64_t, int64_t>> order;
+    for (int64_t e = 0; e < ne; ++e) order.insert({cnt[e], e});
+    std::unordered_map<int64_t, std::vector<int32_t>> lists;
+    auto list_of = [&](int64_t e) -> std::vector<int32_t>& {
+        auto it = lists.find(e);
+        if (it != lists.end()) return it->second;
+        std::vector<int32_t>& v = lists[e];
+        for (int32_t q = start[e0 + e]; q < start[e0 + e + 1]; ++q) v.push_back(q);
+        return v;
+    };
+    auto source = [&](int32_t slot) {
+        auto it = moved.find(slot);
+        return it != moved.end() ? it->second : RedistSrc{slot, slot, -1};
+    };
+    int64_t k = 0;
+    for (;;) {
+        const auto mn = *order.begin();
+        const int64_t cmax = order.rbegin()->first;
+        const auto mx = *order.lower_bound({cmax, INT64_MIN});
+        if (mn.first >= n_min || cmax - mn.first <= 1) break;
+        const int64_t mine = mn.second, maxe = mx.second;
+        const Words4 w = philox4x32_10((uint32_t)k, (uint32_t)((uint64_t)k >> 32), step, TAG_REDIST << 16, P.key.k0,
+                                       P.key.k1);
+        std::vector<int32_t>& give = list_of(maxe);
+        const int64_t r = (int64_t)(u01(w.w0) * (double)give.size());
+        const int32_t slot = give[r];
+        give.erase(give.begin() + r);
+        std::vector<int32_t>& take = list_of(mine);
+        RedistSrc ns;
+        if (!take.empty()) {
+            const int64_t d = (int64_t)(u01(w.w1) * (double)take.size());
+            ns = source(take[d]);
+        } else {
+            ns = source(slot);
+            ns.pos = -(int32_t)(e0 + mine) - 1;
+        }
+        ns.elem = (int32_t)(e0 + mine);
+        moved[slot] = ns;
+        take.push_back(slot);
+        order.erase(mn);
+        order.erase(mx);
+        order.insert({mn.first + 1, mine});
+        order.insert({mx.first - 1, maxe});
+        ++k;
+    }
+    return k;
+}
+
+template <class R>
+pdf_status apply_redistribution(pdf_ens_s* E, const std::unordered_map<int32_t, RedistSrc>& moved, hipStream_t s)
+{
+    const int64_t m = (int64_t)moved.size();
+    if (m == 0) return PDF_OK;
+    if (m > E->redist_cap) {
+        dfree(E->redist_plan);
+        E->redist_cap = 0;
+        pdf_status st = dalloc(&E->redist_plan, 4 * m);
+        if (st != PDF_OK) return st;
+        E->redist_cap = m;
+    }
+    std::vector<int32_t> plan;
+    plan.reserve(4 * m);
+    for (const auto& kv : moved) {
+        plan.push_back(kv.first);
+        plan.push_back(kv.second.pos);
+        plan.push_back(kv.second.prop);
+        plan.push_back(kv.second.elem);
+    }
+    HIP_TRY(hipMemcpyAsync(E->redist_plan, plan.data(), sizeof(int32_t) * plan.size(), hipMemcpyHostToDevice, s));
+    // the other state buffer is free between steps: it stages the gathered states
+    launch_redistribute<R>(cur(E).as<R>(), E->buf[1 - E->cur].as<R>(), E->redist_plan, E->dg.geo, m, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return PDF_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* pdf_last_error(void) { return g_last_error.c_str(); }
@@ -640,6 +753,7 @@ pdf_status pdf_ens_destroy(pdf_ens E)
     free_devgrid(E->dg);
     dfree(E->fb_gn);
     dfree(E->fb_h);
+    dfree(E->redist_plan);
     delete E;
     return PDF_OK;
 }
@@ -887,6 +1001,39 @@ pdf_status pdf_stats(pdf_ens E, int32_t problem, double* out, int32_t out_is_dev
     }
     HIP_TRY(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return check_device_error(E);
+}
+
+pdf_status pdf_redistribute(pdf_ens E, int32_t problem, int32_t n_min, int64_t* moves_out, void* hip_stream)
+{
+    if (moves_out) *moves_out = 0;
+    if (!E || n_min < 0 || problem < -1 || problem >= E->n_problems) {
+        set_error("pdf_redistribute: need n_min >= 0 and -1 <= problem < n_problems");
+        return PDF_E_INVAL;
+    }
+    HIP_TRY(hipSetDevice(E->grid->device));
+    hipStream_t s = as_stream(hip_stream);
+    E->stream = s;
+    if (!E->ctl_valid) {
+        set_error("pdf_redistribute: no element pass since the last control or redistribution");
+        return PDF_E_STATE;
+    }
+    const int64_t ne = E->dg.ne;
+    std::vector<int32_t> start(ne + 1);
+    HIP_TRY(hipMemcpyAsync(start.data(), E->start, sizeof(int32_t) * (ne + 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    pdf_status st = check_device_error(E);
+    if (st != PDF_OK) return st;
+    std::unordered_map<int32_t, RedistSrc> moved;
+    int64_t total = 0;
+    for (int p = 0; p < E->n_problems; ++p)
+        if (problem < 0 || p == problem)
+            total += plan_redistribution(E->h_prm[p], n_min, (uint32_t)E->step, start, moved);
+    st = E->precision == PDF_MIXED ? apply_redistribution<float>(E, moved, s)
+                                   : apply_redistribution<double>(E, moved, s);
+    if (st != PDF_OK) return st;
+    if (total > 0) E->ctl_valid = false;
+    if (moves_out) *moves_out = total;
     return check_device_error(E);
 }
 

@@ -191,4 +191,6 @@ struct pdf_ens_s {
     int ppl_min = 1;                // wavefront capacity suggested by the smallest set-up count
     std::vector<int> tiers;         // particles per lane of the wavefront tiers, ascending
     bool ctl_valid = false;     // the current buffer holds the canonical order of a pass
+    int32_t* redist_plan = nullptr;  // [redist_cap][4] moves of the last redistribution
+    int64_t redist_cap = 0;
 };

@@ -27,7 +27,7 @@ STATUS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "HIP", -4: "MESH", -5: "CAPACIT
 # every symbol include/pdf.h declares
 EXPORTS = ["pdf_grid_create", "pdf_grid_destroy", "pdf_particles_init", "pdf_ens_destroy", "pdf_step",
            "pdf_stats", "pdf_control", "pdf_count", "pdf_particles_export", "pdf_particles_import",
-           "pdf_counters", "pdf_timing", "pdf_set_feedback", "pdf_cfl_dt", "pdf_get_options", "pdf_set_options", "pdf_autotune",
+           "pdf_counters", "pdf_timing", "pdf_set_feedback", "pdf_cfl_dt", "pdf_redistribute", "pdf_get_options", "pdf_set_options", "pdf_autotune",
            "pdf_sync",
            "pdf_last_error"]
 PDF_FP64, PDF_MIXED = 0, 1
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
         "pdf_timing": [vp, C.c_int32, dp, i64p],
         "pdf_set_feedback": [vp, C.c_int32, C.c_double, C.c_int32, vp],
         "pdf_cfl_dt": [vp, C.c_int32, C.c_double, dp, vp],
+        "pdf_redistribute": [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64), vp],
         "pdf_get_options": [vp, C.POINTER(Options)],
         "pdf_set_options": [vp, C.POINTER(Options)],
         "pdf_autotune": [vp, dp, C.c_int32, vp, C.POINTER(Options), ip, dp],
@@ -279,6 +280,12 @@ class Ensemble:
         v = C.c_double()
         _check(load().pdf_cfl_dt(self.h, int(problem), float(cfl), C.byref(v), C.c_void_p(self.stream)))
         return float(v.value)
+
+    def redistribute(self, n_min: int, problem: int = -1) -> int:
+        """Particle redistribution of App. B; returns the number of moves."""
+        v = C.c_int64()
+        _check(load().pdf_redistribute(self.h, int(problem), int(n_min), C.byref(v), C.c_void_p(self.stream)))
+        return int(v.value)
 
     def options(self) -> dict:
         o = Options()

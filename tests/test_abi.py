@@ -53,3 +53,6 @@ def test_option_and_tuning_argument_errors():
     assert L.pdf_get_options(None, ctypes.byref(o)) == -1
     assert L.pdf_autotune(None, None, 1, None, None, None, None) == -1
     assert L.pdf_particles_init(None, None, 0, None, None) == -1
+    moves = ctypes.c_int64(7)
+    assert L.pdf_redistribute(None, -1, 3, ctypes.byref(moves), None) == -1
+    assert moves.value == 0

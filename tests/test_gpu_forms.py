@@ -224,7 +224,7 @@ def test_batched_equals_single_problem_ensembles(gpu):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_graph_replay_is_bitwise_eager(gpu, precision):
     """Steps replayed from captured HIP graphs equal eager steps after every chunk, with
-    eager work (control, export) between replays and a time-step change."""
+    eager work (control, redistribution, export) between replays and a time-step change."""
     _say(f"test_graph_replay_is_bitwise_eager precision={precision}")
     probs = _problems()
     grids = [gpu.Grid(m, f, mo) for m, f, mo, ini, dt in probs]
@@ -240,6 +240,9 @@ def test_graph_replay_is_bitwise_eager(gpu, precision):
         b.step(dts, chunk)
         if ctl:
             assert a.control(40, 70) == b.control(40, 70)
+        if chunk == 4:
+            ra = a.redistribute(45)
+            assert ra > 0 and ra == b.redistribute(45)
         for p in range(len(probs)):
             ea, eb = a.export(problem=p), b.export(problem=p)
             for k in ea:
@@ -295,3 +298,38 @@ def test_mixed_element_estimator(gpu):
         oe.step(1e-3)
         ge.step(1e-3)
     _check_mixed_stats(ge.stats(), oe.stats(), "step 10")
+
+
+def test_mixed_redistribution_invariants(gpu):
+    """App. B redistribution in the mixed form: particle count, pids and weights unchanged,
+    the final counts meet N_min or split evenly, and every moved particle carries the
+    position and properties of a particle of its new element (or its centroid)."""
+    _say("test_mixed_redistribution_invariants")
+    mesh, f, mo, ini = W.redistribution_test(ppe=4)
+    gg = gpu.Grid(mesh, f, mo)
+    ge = gpu.Ensemble(gg, ini, precision=1)
+    frame = O.Grid(mesh, f, mo).export()["frame"]
+    ge.set_feedback(True, 0.5, False)
+    for n in range(4):
+        ge.step(0.05)
+        before = ge.export()
+        c0 = np.bincount(before["elem"], minlength=mesh.n_elems)
+        moves = ge.redistribute(2)
+        after = ge.export()
+        assert moves > 0
+        assert np.array_equal(before["pid"], after["pid"]) and np.array_equal(before["w"], after["w"])
+        c = np.bincount(after["elem"], minlength=mesh.n_elems)
+        assert c.sum() == c0.sum() and (c.min() >= 2 or c.max() - c.min() <= 1)
+        moved = (before["elem"] != after["elem"]) | (before["x"] != after["x"])
+        assert moved.sum() <= moves
+        key = lambda d, i: (d["x"][i], d["y"][i], *d["u"][i], d["om"][i], d["psi"][i])
+        orig = {}
+        for i in np.flatnonzero(~moved):
+            orig.setdefault(int(after["elem"][i]), set()).add(key(after, i))
+        for i in np.flatnonzero(moved):
+            el = int(after["elem"][i])
+            if c0[el] == 0:
+                assert after["x"][i] == (frame[el, 0] + frame[el, 2] + frame[el, 4]) / 3.0
+                assert after["y"][i] == (frame[el, 1] + frame[el, 3] + frame[el, 5]) / 3.0
+            else:
+                assert key(after, i) in orig[el]

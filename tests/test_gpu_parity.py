@@ -390,3 +390,67 @@ def test_element_estimator_parity(gpu):
         rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
     compare_stats(ge.stats(), oe.stats(), _skip_nodes(mesh, excl))
     assert ge.cfl_dt(0.7) == pytest.approx(oe.cfl_dt(0.7), rel=1e-12)
+
+
+@pytest.mark.parametrize("ppe,n_min,dt", [(20, 10, 0.02), (4, 2, 0.05)])
+def test_redistribution_parity(gpu, ppe, n_min, dt):
+    """Particle redistribution of App. B after every step of the Sec. 3.7 test (stretched
+    strip, fed-back mean with alpha = 0.5): the same moves as the oracle, hence the same
+    particles in every element; the second case empties elements (centroid placement)."""
+    _say(f"test_redistribution_parity ppe={ppe} n_min={n_min}")
+    mesh, f, mo, ini = W.redistribution_test(ppe=ppe)
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    oe.feedback(0.5, False)
+    ge.set_feedback(True, 0.5, False)
+    excl = set()
+    total = 0
+    for n in range(10):
+        oe.step(dt)
+        ge.step(dt)
+        mo_, mg = oe.redistribute(n_min), ge.redistribute(n_min)
+        assert mo_ == mg, (n, mo_, mg)
+        total += mg
+        if mg:
+            with pytest.raises(gpu.PdfError):
+                ge.redistribute(n_min)
+        oe.feedback(0.5, False)
+        rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+        assert not excl, n
+    assert total > 100
+    oe.step(dt)
+    ge.step(dt)
+    compare_states(ge.export(), oe.export(), frame, _length(mesh))
+    compare_stats(ge.stats(), oe.stats())
+
+
+def test_redistribution_batched(gpu):
+    """Per-problem redistribution in a batched ensemble: every problem, then one problem
+    only, each equal to its own oracle ensemble (key seed ^ problem << 32)."""
+    _say("test_redistribution_batched")
+    mo = W.model_constants(nu=0.0)
+    cases = []
+    for p, (nx, ny, ppe) in enumerate(((8, 12, 6), (10, 8, 5))):
+        mesh, f, mo, ini = W.redistribution_test(nx=nx, ny=ny, ppe=ppe, seed=100 + p)
+        cases.append((mesh, f, ini))
+    grids = [gpu.Grid(m, f, mo) for m, f, _ in cases]
+    bat = gpu.Ensemble(grids, [c[2] for c in cases])
+    oes = []
+    for p, (m, f, d) in enumerate(cases):
+        dd = dict(d)
+        dd["seed"] = int(d["seed"]) ^ (p << 32)
+        oes.append((O.Ensemble(O.Grid(m, f, mo), dd), O.Grid(m, f, mo).export()["frame"], m))
+    for n in range(4):
+        bat.step([0.05, 0.05])
+        for o, _, _ in oes:
+            o.step(0.05)
+        if n % 2 == 0:
+            mg = bat.redistribute(3)
+            mo_ = sum(o.redistribute(3) for o, _, _ in oes)
+        else:
+            mg = bat.redistribute(3, problem=1)
+            mo_ = oes[1][0].redistribute(3)
+        assert mg == mo_ and mg > 0, (n, mg, mo_)
+        for p, (o, frame, m) in enumerate(oes):
+            rep, excl = compare_states(bat.export(problem=p), o.export(), frame, _length(m))
+            assert not excl
