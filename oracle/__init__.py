@@ -44,7 +44,7 @@ class InitDesc(C.Structure):
                 ("src_x", C.c_double), ("src_y", C.c_double), ("src_r", C.c_double),
                 ("src_continuous", C.c_int32), ("bins", C.c_int32 * 3),
                 ("min_per_bin", C.c_int32), ("seed", C.c_uint64), ("problem", C.c_int32),
-                ("estimator", C.c_int32)]
+                ("estimator", C.c_int32), ("conditioning", C.c_int32)]
 
 
 _lib = None
@@ -89,6 +89,7 @@ def lib():
         "orc_control": (C.c_int32, [P, C.c_int32, C.c_int32, i64p]),
         "orc_counters": (None, [P, i64p]),
         "orc_bin_element": (C.c_int32, [C.c_int32, dp, u64p, ip, C.c_int32, ip, ip]),
+        "orc_project_element": (C.c_int32, [C.c_int32, dp, dp, dp, u64p, C.c_int32, C.c_int32, dp, ip, ip, dp]),
         "orc_tm": (C.c_double, [P, C.c_int32]),
     }
     for name, (res, args) in sig.items():
@@ -147,6 +148,23 @@ def bin_element(u, pid, bins, min_per_bin=2):
     cp = lib().orc_bin_element(n, _p(u, C.c_double), _p(pid, C.c_uint64), bb, min_per_bin,
                                _p(pos, C.c_int32), _p(b, C.c_int32))
     return cp, pos, b
+
+
+def project_element(u, psi, w, pid, nc, min_per_bin=2):
+    """Fox's projection of one element (Eqs. 64-66): (bins used, key, pos, bin, alpha)."""
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 3)
+    psi = np.ascontiguousarray(psi, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    pid = np.ascontiguousarray(pid, dtype=np.uint64)
+    n = u.shape[0]
+    key = np.empty(n)
+    pos = np.empty(n, dtype=np.int32)
+    b = np.empty(n, dtype=np.int32)
+    alpha = np.empty(3)
+    cp = lib().orc_project_element(n, _p(u, C.c_double), _p(psi, C.c_double), _p(w, C.c_double),
+                                   _p(pid, C.c_uint64), int(nc), int(min_per_bin), _p(key, C.c_double),
+                                   _p(pos, C.c_int32), _p(b, C.c_int32), _p(alpha, C.c_double))
+    return cp, key, pos, b, alpha
 
 
 # ------------------------------------------------------------------------ grid / ensemble
@@ -208,6 +226,7 @@ def make_init(d: dict, problem: int = 0) -> InitDesc:
         s.bins[i] = int(d["bins"][i])
     s.min_per_bin = int(d["min_per_bin"]); s.seed = int(d["seed"]); s.problem = int(problem)
     s.estimator = int(d.get("estimator", 0))
+    s.conditioning = int(d.get("conditioning", 0))
     return s
 
 

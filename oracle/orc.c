@@ -753,6 +753,147 @@ static int32_t canonical_order(int64_t* idx, int32_t n, const part* P, const int
     return Cp;
 }
 
+/* Fox's projection conditioning (Eqs. 64-66).  Over the particles of one element, with
+   weights w: means, then the central second moments <u_a u_b>, <u_a phi'>, <phi'^2>;
+   rho_a and rho_ab of Eq. (66); the projection vector alpha solves rho_ab alpha_b = rho_a
+   (Eq. 65); the projected velocity (Eq. 64) is taken of the normalised fluctuations,
+   U_rho = sum_a alpha_a (U_a - <U_a>) / <u_a^2>^(1/2), the combination for which a joint
+   Gaussian PDF makes <phi'|U> a function of U_rho alone.  Degenerate samples: a component
+   without variance (standard deviation at most 1e-12 times its largest magnitude in the
+   element, i.e. a spread made of rounding), and a component that is a linear combination
+   of the earlier ones (taken in the order U1, U2, U3; remaining diagonal of the Cholesky
+   factor of rho below 1e-12), get alpha = 0; without scalar variance (the same test on
+   psi) alpha = 0 and every key is 0.
+   The particles are then sorted by (U_rho, pid) and divided into
+   min(nc, max(1, floor(n / min_per_bin))) equal-count intervals. */
+static void projection_keys(int32_t n, const int64_t* idx, const part* P, double* key, double alpha[3])
+{
+    double W = 0.0, mu[3] = { 0, 0, 0 }, mp = 0.0, umax[3] = { 0, 0, 0 }, pmax = 0.0;
+    for (int32_t r = 0; r < n; ++r) {
+        const part* q = &P[idx[r]];
+        W += q->w;
+        for (int a = 0; a < 3; ++a) {
+            mu[a] += q->w * q->u[a];
+            umax[a] = fmax(umax[a], fabs(q->u[a]));
+        }
+        mp += q->w * q->psi;
+        pmax = fmax(pmax, fabs(q->psi));
+    }
+    for (int a = 0; a < 3; ++a) mu[a] /= W;
+    mp /= W;
+    double Cuu[3][3] = { { 0 } }, Cup[3] = { 0, 0, 0 }, Cpp = 0.0;
+    for (int32_t r = 0; r < n; ++r) {
+        const part* q = &P[idx[r]];
+        double d[3] = { q->u[0] - mu[0], q->u[1] - mu[1], q->u[2] - mu[2] };
+        double dp = q->psi - mp;
+        for (int a = 0; a < 3; ++a) {
+            for (int b = 0; b < 3; ++b) Cuu[a][b] += q->w * d[a] * d[b];
+            Cup[a] += q->w * d[a] * dp;
+        }
+        Cpp += q->w * dp * dp;
+    }
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b) Cuu[a][b] /= W;
+        Cup[a] /= W;
+    }
+    Cpp /= W;
+    double sd[3];
+    for (int a = 0; a < 3; ++a) {
+        sd[a] = sqrt(Cuu[a][a]);
+        if (!(sd[a] > 1e-12 * umax[a])) sd[a] = 0.0;
+        alpha[a] = 0.0;
+    }
+    if (sqrt(Cpp) > 1e-12 * pmax) {
+        /* Eq. (66) */
+        double rho[3][3], rv[3];
+        for (int a = 0; a < 3; ++a) {
+            rv[a] = sd[a] > 0.0 ? Cup[a] / (sd[a] * sqrt(Cpp)) : 0.0;
+            for (int b = 0; b < 3; ++b) rho[a][b] = (sd[a] > 0.0 && sd[b] > 0.0) ? Cuu[a][b] / (sd[a] * sd[b]) : 0.0;
+        }
+        /* Eq. (65) on the independent components: Cholesky factor L of rho restricted to
+           them, then forward and back substitution */
+        int sel[3], k = 0;
+        double L[3][3] = { { 0 } };
+        for (int a = 0; a < 3; ++a) {
+            if (!(sd[a] > 0.0)) continue;
+            double l[3], dd = rho[a][a];
+            for (int i = 0; i < k; ++i) {
+                double s = rho[a][sel[i]];
+                for (int j = 0; j < i; ++j) s -= L[i][j] * l[j];
+                l[i] = s / L[i][i];
+                dd -= l[i] * l[i];
+            }
+            if (!(dd > 1e-12)) continue;
+            for (int i = 0; i < k; ++i) L[k][i] = l[i];
+            L[k][k] = sqrt(dd);
+            sel[k++] = a;
+        }
+        double z[3];
+        for (int i = 0; i < k; ++i) {
+            double s = rv[sel[i]];
+            for (int j = 0; j < i; ++j) s -= L[i][j] * z[j];
+            z[i] = s / L[i][i];
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double s = z[i];
+            for (int j = i + 1; j < k; ++j) s -= L[j][i] * alpha[sel[j]];
+            alpha[sel[i]] = s / L[i][i];
+        }
+    }
+    /* Eq. (64) on the normalised fluctuations */
+    for (int32_t r = 0; r < n; ++r) {
+        const part* q = &P[idx[r]];
+        double v = 0.0;
+        for (int a = 0; a < 3; ++a)
+            if (alpha[a] != 0.0) v += alpha[a] * ((q->u[a] - mu[a]) / sd[a]);
+        key[r] = v;
+    }
+}
+
+/* sorts idx[0..n) by (U_rho, pid); returns the number of intervals */
+static int32_t projection_order(int64_t* idx, int32_t n, const part* P, int32_t nc, int32_t m, double alpha[3])
+{
+    if (n == 0) return 1;
+    double* key = (double*)malloc(sizeof(double) * n);
+    projection_keys(n, idx, P, key, alpha);
+    for (int32_t i = 1; i < n; ++i) {   /* insertion sort of (key, idx) pairs */
+        int64_t t = idx[i];
+        double kt = key[i];
+        int32_t j = i - 1;
+        while (j >= 0 && (key[j] > kt || (key[j] == kt && P[idx[j]].pid > P[t].pid))) {
+            idx[j + 1] = idx[j];
+            key[j + 1] = key[j];
+            --j;
+        }
+        idx[j + 1] = t;
+        key[j + 1] = kt;
+    }
+    free(key);
+    int64_t q = n / m;
+    if (q < 1) q = 1;
+    return (int32_t)(nc < q ? nc : q);
+}
+
+int32_t orc_project_element(int32_t n, const double* u, const double* psi, const double* w, const uint64_t* pid,
+                            int32_t nc, int32_t min_per_bin, double* key, int32_t* pos, int32_t* bin,
+                            double alpha[3])
+{
+    part* P = (part*)calloc(n > 0 ? n : 1, sizeof(part));
+    int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+    for (int32_t i = 0; i < n; ++i) {
+        P[i].u[0] = u[3 * i]; P[i].u[1] = u[3 * i + 1]; P[i].u[2] = u[3 * i + 2];
+        P[i].psi = psi[i]; P[i].w = w[i]; P[i].pid = pid[i]; idx[i] = i;
+    }
+    projection_keys(n, idx, P, key, alpha);
+    int32_t Cp = projection_order(idx, n, P, nc, min_per_bin, alpha);
+    for (int32_t r = 0; r < n; ++r) {
+        pos[idx[r]] = r;
+        bin[idx[r]] = (int32_t)(((int64_t)Cp * r) / n);
+    }
+    free(P); free(idx);
+    return Cp;
+}
+
 int32_t orc_bin_element(int32_t n, const double* u, const uint64_t* pid, const int32_t bins[3],
                         int32_t min_per_bin, int32_t* pos, int32_t* bin)
 {
@@ -819,7 +960,9 @@ static void element_pass(orc_ens* E, double dt, int mix)
         int32_t n = (int32_t)(E->seg[e + 1] - E->seg[e]);
         if (n == 0) continue;
         int64_t* idx = E->order + E->seg[e];
-        int32_t Cp = canonical_order(idx, n, E->p, E->d.bins, E->d.min_per_bin);
+        double alpha[3];
+        int32_t Cp = E->d.conditioning == 1 ? projection_order(idx, n, E->p, E->d.bins[0], E->d.min_per_bin, alpha)
+                                            : canonical_order(idx, n, E->p, E->d.bins, E->d.min_per_bin);
         if (!mix) continue;
         double fmix = dt / E->tm[e];
         if (fmix > 1.0) fmix = 1.0;
@@ -964,7 +1107,7 @@ orc_ens* orc_init(orc_grid* g, const orc_init_desc* d, char* err, int32_t errlen
 {
     if (!g || !d || d->ppe < 0 || d->min_per_bin < 1 || d->bins[0] < 1 || d->bins[1] < 1 || d->bins[2] < 1 ||
         !(d->omega_shape >= 1.0) || !(d->u_sigma >= 0.0) || !(d->src_r >= 0.0) || d->estimator < 0 ||
-        d->estimator > 1) {
+        d->estimator > 1 || d->conditioning < 0 || d->conditioning > 1) {
         seterr(err, errlen, "bad init descriptor");
         return NULL;
     }

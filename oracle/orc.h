@@ -34,6 +34,8 @@ typedef struct {
     uint64_t seed; int32_t problem;
     int32_t estimator;   /* 0: P1-weighted nodal moments and P1 interpolation;
                             1: element means averaged to the nodes, element-averaged fields (Sec. 3.3) */
+    int32_t conditioning; /* 0: sort-and-divide velocity bins (Sec. 3.5, App. A);
+                             1: Fox's projection on one velocity direction, bins[0] intervals (Eqs. 64-66) */
 } orc_init_desc;
 
 /* --- units (used by the pins) --- */
@@ -95,6 +97,12 @@ void orc_counters(const orc_ens*, int64_t out[8]);
    element given its velocities and pids; returns bins used (C') */
 int32_t orc_bin_element(int32_t n, const double* u /*[n][3]*/, const uint64_t* pid,
                         const int32_t bins[3], int32_t min_per_bin, int32_t* pos, int32_t* bin);
+/* Fox's projection of one element (Eqs. 64-66): projected velocity key[n], canonical
+   positions and bins (nc intervals, at least min_per_bin particles each), and the
+   projection vector alpha[3] of the normalised velocities; returns bins used */
+int32_t orc_project_element(int32_t n, const double* u /*[n][3]*/, const double* psi, const double* w,
+                            const uint64_t* pid, int32_t nc, int32_t min_per_bin, double* key, int32_t* pos,
+                            int32_t* bin, double alpha[3]);
 /* micromixing timescale of element e (Eq. 25 at the centroid) */
 double orc_tm(const orc_ens*, int32_t e);
 
