@@ -76,6 +76,20 @@ enum { PDF_FP64 = 0, PDF_MIXED = 1 };
  *                   its element's three nodal values. */
 enum { PDF_EST_P1 = 0, PDF_EST_ELEMENT = 1 };
 
+/* conditioning of the scalar mean <phi|V> of the IECM model (pdf_init_desc.conditioning):
+ *  PDF_COND_BINS        sort-and-divide velocity bins, bins[0] x bins[1] x bins[2] (Sec. 3.5,
+ *                       App. A);
+ *  PDF_COND_PROJECTION  Fox's projection (Eqs. 64-66): per element, alpha solves
+ *                       rho_ab alpha_b = rho_a with the normalised velocity and velocity-scalar
+ *                       correlations; the particles are ordered by the projected normalised
+ *                       velocity sum_a alpha_a (U_a - <U_a>) / <u_a^2>^(1/2) (ties by pid) and
+ *                       divided into min(bins[0], max(1, n / min_per_bin)) equal-count
+ *                       intervals (bins[1], bins[2] unused).  Components without variance
+ *                       (spread below 1e-12 of their largest magnitude) or linearly dependent
+ *                       on earlier ones (order U1, U2, U3) get alpha = 0; a scalar without
+ *                       variance gives alpha = 0, i.e. one key for all particles. */
+enum { PDF_COND_BINS = 0, PDF_COND_PROJECTION = 1 };
+
 /* boundary kinds of element edges; edge k of a triangle is the edge opposite vertex k */
 enum { PDF_EDGE_INTERIOR = 0, PDF_EDGE_WALL = 1, PDF_EDGE_SLIP = 2, PDF_EDGE_PERIODIC = 3 };
 
@@ -137,7 +151,8 @@ typedef struct {
  *                 word XOR the problem's index in the ensemble);
  *  capacity       particle slots for this problem (0: max(2 x ppe x n_elems, 1024));
  *                 the ensemble allocates the sum over its problems;
- *  estimator      PDF_EST_P1 or PDF_EST_ELEMENT (the same for every problem). */
+ *  estimator      PDF_EST_P1 or PDF_EST_ELEMENT (the same for every problem);
+ *  conditioning   PDF_COND_BINS or PDF_COND_PROJECTION (may differ between problems). */
 typedef struct {
     int32_t ppe;
     double u_sigma, omega_shape;
@@ -149,6 +164,7 @@ typedef struct {
     uint64_t seed;
     int64_t capacity;
     int32_t estimator;
+    int32_t conditioning;
 } pdf_init_desc;
 
 /* Result of pdf_control. */

@@ -54,6 +54,7 @@ struct ElementArgs {
     double* gkey;
     int32_t* gord;
     double* gu3;
+    int32_t any_proj;     // some problem conditions by Fox's projection
 };
 
 template <class R>

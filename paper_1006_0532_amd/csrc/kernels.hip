@@ -657,6 +657,99 @@ __device__ __forceinline__ void add_partials(Acc<R> (&acc)[3][NPART], const R (&
     }
 }
 
+// Fox's projection (Eqs. 64-66) from an element's central weighted sums
+// cs = {uu 00, 11, 22, 01, 02, 12, u0 phi', u1 phi', u2 phi', phi'^2}, total weight W and the
+// largest magnitudes of U_a (umax) and psi (pmax): the standard deviations sd (0 for a
+// spread at rounding level) and the projection vector alpha solving rho_ab alpha_b = rho_a
+// on the independent components (Cholesky of rho in the order U1, U2, U3, dropping a
+// component whose remaining diagonal is at most 1e-12).  The same steps on every lane.
+__device__ __noinline__ void fox_alpha(double W, const double (&cs)[10], const double (&umax)[3], double pmax,
+                                       double (&alpha)[3], double (&sd)[3])
+{
+    const int ix[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    double Cuu[3][3], Cup[3];
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b) Cuu[a][b] = cs[ix[a][b]] / W;
+        Cup[a] = cs[6 + a] / W;
+    }
+    const double Cpp = cs[9] / W;
+    for (int a = 0; a < 3; ++a) {
+        sd[a] = sqrt(Cuu[a][a]);
+        if (!(sd[a] > 1e-12 * umax[a])) sd[a] = 0.0;
+        alpha[a] = 0.0;
+    }
+    if (!(sqrt(Cpp) > 1e-12 * pmax)) return;
+    double rho[3][3], rv[3];
+    for (int a = 0; a < 3; ++a) {
+        rv[a] = sd[a] > 0.0 ? Cup[a] / (sd[a] * sqrt(Cpp)) : 0.0;
+        for (int b = 0; b < 3; ++b) rho[a][b] = (sd[a] > 0.0 && sd[b] > 0.0) ? Cuu[a][b] / (sd[a] * sd[b]) : 0.0;
+    }
+    int sel[3] = {0, 0, 0}, k = 0;
+    double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int a = 0; a < 3; ++a) {
+        if (!(sd[a] > 0.0)) continue;
+        double l[3] = {0, 0, 0}, dd = rho[a][a];
+        for (int i = 0; i < k; ++i) {
+            double t = rho[a][sel[i]];
+            for (int j = 0; j < i; ++j) t -= L[i][j] * l[j];
+            l[i] = t / L[i][i];
+            dd -= l[i] * l[i];
+        }
+        if (!(dd > 1e-12)) continue;
+        for (int i = 0; i < k; ++i) L[k][i] = l[i];
+        L[k][k] = sqrt(dd);
+        sel[k++] = a;
+    }
+    double z[3] = {0, 0, 0};
+    for (int i = 0; i < k; ++i) {
+        double t = rv[sel[i]];
+        for (int j = 0; j < i; ++j) t -= L[i][j] * z[j];
+        z[i] = t / L[i][i];
+    }
+    for (int i = k - 1; i >= 0; --i) {
+        double t = z[i];
+        for (int j = i + 1; j < k; ++j) t -= L[j][i] * alpha[sel[j]];
+        alpha[sel[i]] = t / L[i][i];
+    }
+}
+
+// projected velocity of Eq. (64) on the normalised fluctuations
+__device__ __forceinline__ double fox_key(const double (&alpha)[3], const double (&sd)[3], const double (&mu)[3],
+                                          double u0, double u1, double u2)
+{
+    const double u[3] = {u0, u1, u2};
+    double v = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (alpha[a] != 0.0) v += alpha[a] * ((u[a] - mu[a]) / sd[a]);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max_double(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// sums (max != 0: maxima) of k <= 16 values over a workgroup; every thread gets the results
+template <int NT>
+__device__ __forceinline__ void block_reduce(double* v, int k, bool max, double* scratch)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int q = 0; q < k; ++q) {
+        const double t = max ? wave_max_double(v[q]) : wave_sum_double(v[q]);
+        if (lane == 0) scratch[wid * 16 + q] = t;
+    }
+    __syncthreads();
+    for (int q = 0; q < k; ++q) {
+        double t = 0.0;   // the maxima taken here are of magnitudes
+        for (int w = 0; w < NT / 64; ++w) t = max ? fmax(t, scratch[w * 16 + q]) : t + scratch[w * 16 + q];
+        v[q] = t;
+    }
+    __syncthreads();
+}
+
 template <int NT, class R>
 __device__ __forceinline__ void element_body(const ElementArgs<R>& a, int32_t e, int64_t s0, int n, R* U0, R* U1,
                                              R* U2, uint64_t* PID, SortKey* kp, int32_t* ordA, int32_t* ordB,
@@ -675,16 +768,60 @@ __device__ __forceinline__ void element_body(const ElementArgs<R>& a, int32_t e,
         ordA[j] = j;
     }
     __syncthreads();
+    // Fox's projection: element moments, projection vector, projected velocities
+    const bool proj = P.conditioning == 1;
+    double fmu[3] = {0, 0, 0}, falpha[3] = {0, 0, 0}, fsd[3] = {0, 0, 0};
+    if (proj) {
+        double* scratch = reinterpret_cast<double*>(red);
+        double m[5] = {0, 0, 0, 0, 0}, mx[4] = {0, 0, 0, 0};
+        for (int j = tid; j < n; j += NT) {
+            const int64_t gi = a.idx[s0 + j];
+            const double w = a.in.w[gi], ps = a.in.psi[gi];
+            const double u[3] = {U0[j], U1[j], U2[j]};
+            m[0] += w;
+            for (int c = 0; c < 3; ++c) {
+                m[1 + c] += w * u[c];
+                mx[c] = fmax(mx[c], fabs(u[c]));
+            }
+            m[4] += w * ps;
+            mx[3] = fmax(mx[3], fabs(ps));
+        }
+        block_reduce<NT>(m, 5, false, scratch);
+        block_reduce<NT>(mx, 4, true, scratch);
+        for (int c = 0; c < 3; ++c) fmu[c] = m[1 + c] / m[0];
+        const double mp = m[4] / m[0];
+        double cs[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int j = tid; j < n; j += NT) {
+            const int64_t gi = a.idx[s0 + j];
+            const double w = a.in.w[gi];
+            const double d0 = (double)U0[j] - fmu[0], d1 = (double)U1[j] - fmu[1], d2 = (double)U2[j] - fmu[2];
+            const double dp = (double)a.in.psi[gi] - mp;
+            cs[0] += w * d0 * d0;
+            cs[1] += w * d1 * d1;
+            cs[2] += w * d2 * d2;
+            cs[3] += w * d0 * d1;
+            cs[4] += w * d0 * d2;
+            cs[5] += w * d1 * d2;
+            cs[6] += w * d0 * dp;
+            cs[7] += w * d1 * dp;
+            cs[8] += w * d2 * dp;
+            cs[9] += w * dp * dp;
+        }
+        block_reduce<NT>(cs, 10, false, scratch);
+        const double umax[3] = {mx[0], mx[1], mx[2]};
+        fox_alpha(m[0], cs, umax, mx[3], falpha, fsd);
+    }
     int g0, g1, g2;
-    const int Cp = bin_structure(n, P.bins0, P.bins1, P.bins2, P.minpb, g0, g1, g2);
+    const int Cp = bin_structure(n, P.bins0, proj ? 1 : P.bins1, proj ? 1 : P.bins2, P.minpb, g0, g1, g2);
     const int gl[3] = {g0, g1, g2};
-    // three levels: sort every group of the previous level by (U_l, pid) (rank sort)
+    // three levels: sort every group of the previous level by (U_l, pid) (rank sort); one
+    // level by the projected velocity with Fox's projection
     long long C = 1;
-    for (int l = 0; l < 3; ++l) {
+    for (int l = 0; l < (proj ? 1 : 3); ++l) {
         const R* Ul = l == 0 ? U0 : (l == 1 ? U1 : U2);
         for (int pos = tid; pos < n; pos += NT) {
             const int j = clampi(ordA[pos], n);
-            kp[pos].k = order_bits(Ul[j]);
+            kp[pos].k = proj ? order_bits(fox_key(falpha, fsd, fmu, U0[j], U1[j], U2[j])) : order_bits(Ul[j]);
             kp[pos].p = PID[j];
         }
         __syncthreads();
@@ -853,7 +990,7 @@ struct WaveBlock {
 // Tiers of increasing capacity: a launch takes the elements with n_below < n <= 64 PPL
 // (n_below = -1 for the first tier, so empty elements are handled there); the last tier
 // puts larger elements on the workgroup kernel's worklist (last != 0).
-template <int PPL, class R>
+template <int PPL, class R, bool PROJ>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WaveBlock<PPL>::per_simd)))
 k_element_wave(ElementArgs<R> a, int n_below, int last)
 {
@@ -914,18 +1051,76 @@ k_element_wave(ElementArgs<R> a, int n_below, int last)
             pd[r] = a.in.pid[gi[r]];
         }
     }
+    // Fox's projection (instantiated only for ensembles that use it): element moments by
+    // wavefront reductions, the projection vector, and the projected velocities as keys
+    const bool proj = PROJ && P.conditioning == 1;
+    double fk[PROJ ? PPL : 1];
+    if constexpr (PROJ) {
+        if (proj) {
+            double m[5] = {0, 0, 0, 0, 0}, mx[4] = {0, 0, 0, 0};
+            R wq[PPL], pq[PPL];
+#pragma unroll
+            for (int r = 0; r < PPL; ++r) {
+                wq[r] = pq[r] = R(0);
+                if (lane + 64 * r < n) {
+                    wq[r] = a.in.w[gi[r]];
+                    pq[r] = a.in.psi[gi[r]];
+                    const double w = wq[r], u[3] = {U0[r], U1[r], U2[r]};
+                    m[0] += w;
+                    for (int c = 0; c < 3; ++c) {
+                        m[1 + c] += w * u[c];
+                        mx[c] = fmax(mx[c], fabs(u[c]));
+                    }
+                    m[4] += w * (double)pq[r];
+                    mx[3] = fmax(mx[3], fabs((double)pq[r]));
+                }
+            }
+            for (int q = 0; q < 5; ++q) m[q] = wave_sum_double(m[q]);
+            for (int q = 0; q < 4; ++q) mx[q] = wave_max_double(mx[q]);
+            const double mu[3] = {m[1] / m[0], m[2] / m[0], m[3] / m[0]};
+            const double mp = m[4] / m[0];
+            double cs[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int r = 0; r < PPL; ++r)
+                if (lane + 64 * r < n) {
+                    const double w = wq[r];
+                    const double d0 = (double)U0[r] - mu[0], d1 = (double)U1[r] - mu[1], d2 = (double)U2[r] - mu[2];
+                    const double dp = (double)pq[r] - mp;
+                    cs[0] += w * d0 * d0;
+                    cs[1] += w * d1 * d1;
+                    cs[2] += w * d2 * d2;
+                    cs[3] += w * d0 * d1;
+                    cs[4] += w * d0 * d2;
+                    cs[5] += w * d1 * d2;
+                    cs[6] += w * d0 * dp;
+                    cs[7] += w * d1 * dp;
+                    cs[8] += w * d2 * dp;
+                    cs[9] += w * dp * dp;
+                }
+            for (int q = 0; q < 10; ++q) cs[q] = wave_sum_double(cs[q]);
+            double alpha[3], sd[3];
+            const double umax[3] = {mx[0], mx[1], mx[2]};
+            fox_alpha(m[0], cs, umax, mx[3], alpha, sd);
+#pragma unroll
+            for (int r = 0; r < PPL; ++r) fk[r] = fox_key(alpha, sd, mu, U0[r], U1[r], U2[r]);
+        }
+    }
     int g0, g1, g2;
-    const int Cp = bin_structure(n, P.bins0, P.bins1, P.bins2, P.minpb, g0, g1, g2);
+    const int Cp = bin_structure(n, P.bins0, proj ? 1 : P.bins1, proj ? 1 : P.bins2, P.minpb, g0, g1, g2);
     const int gl[3] = {g0, g1, g2};
     long long C = 1;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
+        if (proj && l > 0) break;
         uint64_t mk[PPL];
         int lo[PPL], hi[PPL];
         uint64_t kmin = ~0ull, kmax = 0ull;
 #pragma unroll
         for (int r = 0; r < PPL; ++r) {
-            mk[r] = order_bits(l == 0 ? U0[r] : (l == 1 ? U1[r] : U2[r]));
+            if constexpr (PROJ)
+                mk[r] = proj ? order_bits(fk[r]) : order_bits(l == 0 ? U0[r] : (l == 1 ? U1[r] : U2[r]));
+            else
+                mk[r] = order_bits(l == 0 ? U0[r] : (l == 1 ? U1[r] : U2[r]));
             const int t = div_small((int)C * pos[r], n);
             lo[r] = div_small(t * n + (int)C - 1, (int)C);
             hi[r] = div_small((t + 1) * n + (int)C - 1, (int)C);
@@ -1672,8 +1867,12 @@ template <int PPL, class R>
 static void launch_wave_tier(const ElementArgs<R>& a, int n_below, int last, hipStream_t s)
 {
     constexpr int WPB = WaveBlock<PPL>::waves;
-    hipLaunchKernelGGL((k_element_wave<PPL, R>), dim3((unsigned)((a.ne + WPB - 1) / WPB)), dim3(64 * WPB), 0, s, a,
-                       n_below, last);
+    if (a.any_proj)
+        hipLaunchKernelGGL((k_element_wave<PPL, R, true>), dim3((unsigned)((a.ne + WPB - 1) / WPB)), dim3(64 * WPB), 0,
+                           s, a, n_below, last);
+    else
+        hipLaunchKernelGGL((k_element_wave<PPL, R, false>), dim3((unsigned)((a.ne + WPB - 1) / WPB)), dim3(64 * WPB), 0,
+                           s, a, n_below, last);
 }
 template <class R>
 void launch_element_pass(const ElementArgs<R>& a, const int* tiers, int n_tiers, hipStream_t s)

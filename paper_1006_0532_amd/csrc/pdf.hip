@@ -151,6 +151,7 @@ pdf_status regroup(pdf_ens_s* E, bool mix, bool counts_ready, bool advance_step,
     ea.gkey = E->gkey;
     ea.gord = E->gord;
     ea.gu3 = E->gu3;
+    ea.any_proj = E->any_proj ? 1 : 0;
     {
         Timed t(E, T_ELEMENT, s);
         launch_element_pass<R>(ea, E->tiers.data(), (int)E->tiers.size(), s);
@@ -780,7 +781,8 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
             !std::isfinite(d.omega_shape) || !std::isfinite(d.src_x) || !std::isfinite(d.src_y) ||
             !std::isfinite(d.src_r) || (d.precision != PDF_FP64 && d.precision != PDF_MIXED) ||
             d.precision != descs[0].precision || d.capacity < 0 || g->device != grids[0]->device ||
-            (d.estimator != PDF_EST_P1 && d.estimator != PDF_EST_ELEMENT) || d.estimator != descs[0].estimator) {
+            (d.estimator != PDF_EST_P1 && d.estimator != PDF_EST_ELEMENT) || d.estimator != descs[0].estimator ||
+            (d.conditioning != PDF_COND_BINS && d.conditioning != PDF_COND_PROJECTION)) {
             set_error("pdf_particles_init: invalid descriptor (bins product <= 1024, omega_shape >= 1, one "
                       "precision, estimator and device for all problems)");
             return PDF_E_INVAL;
@@ -838,6 +840,8 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
             P.minpb = d.min_per_bin;
             P.ppe = d.ppe > 0 ? d.ppe : 1;
             P.estimator = d.estimator;
+            P.conditioning = d.conditioning;
+            if (d.conditioning == PDF_COND_PROJECTION) E->any_proj = true;
             P.eoff = eo;
             P.ne = g->ne;
             P.noff = no;

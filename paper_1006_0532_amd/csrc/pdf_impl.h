@@ -89,6 +89,7 @@ struct ProbParams {
     int32_t bins0, bins1, bins2, minpb;
     int32_t ppe;
     int32_t estimator;             // 0: P1-weighted moments, P1 fields; 1: element means to nodes
+    int32_t conditioning;          // 0: sort-and-divide bins; 1: Fox's projection (Eqs. 64-66)
     int64_t eoff, ne;              // element range in the ensemble
     int64_t noff, nn;              // node range
     int64_t soff;                  // first set-up slot
@@ -191,6 +192,7 @@ struct pdf_ens_s {
     int ppl_min = 1;                // wavefront capacity suggested by the smallest set-up count
     std::vector<int> tiers;         // particles per lane of the wavefront tiers, ascending
     bool ctl_valid = false;     // the current buffer holds the canonical order of a pass
+    bool any_proj = false;      // some problem conditions by Fox's projection
     int32_t* redist_plan = nullptr;  // [redist_cap][4] moves of the last redistribution
     int64_t redist_cap = 0;
 };

@@ -58,7 +58,7 @@ class InitDesc(C.Structure):
                 ("src_x", C.c_double), ("src_y", C.c_double), ("src_r", C.c_double),
                 ("src_continuous", C.c_int32), ("bins", C.c_int32 * 3), ("min_per_bin", C.c_int32),
                 ("precision", C.c_int32), ("seed", C.c_uint64), ("capacity", C.c_int64),
-                ("estimator", C.c_int32)]
+                ("estimator", C.c_int32), ("conditioning", C.c_int32)]
 
 
 class Options(C.Structure):
@@ -173,6 +173,7 @@ def make_init(d: dict, capacity: int = 0, precision: int = 0) -> InitDesc:
     s.min_per_bin = int(d["min_per_bin"]); s.precision = int(precision); s.seed = int(d["seed"])
     s.capacity = int(capacity or d.get("capacity", 0))
     s.estimator = int(d.get("estimator", 0))
+    s.conditioning = int(d.get("conditioning", 0))
     return s
 
 

@@ -333,3 +333,18 @@ def test_mixed_redistribution_invariants(gpu):
                 assert after["y"][i] == (frame[el, 1] + frame[el, 3] + frame[el, 5]) / 3.0
             else:
                 assert key(after, i) in orig[el]
+
+
+def test_mixed_projection_conditioning(gpu):
+    """Fox's projection in the mixed form: statistics within the mixed-form bounds of the
+    FP64 oracle after a few steps."""
+    _say("test_mixed_projection_conditioning")
+    mesh, f, mo, ini = W.channel_small(nx=20, ny=24)
+    ini = dict(ini, bins=(5, 1, 1), conditioning=1, src_r=0.4)
+    og = O.Grid(mesh, f, mo)
+    oe = O.Ensemble(og, ini)
+    ge = gpu.Ensemble(gpu.Grid(mesh, f, mo), ini, precision=1)
+    for n in range(5):
+        oe.step(1e-3)
+        ge.step(1e-3)
+    _check_mixed_stats(ge.stats(), oe.stats(), "projection, 5 steps")

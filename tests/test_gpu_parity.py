@@ -454,3 +454,70 @@ def test_redistribution_batched(gpu):
         for p, (o, frame, m) in enumerate(oes):
             rep, excl = compare_states(bat.export(problem=p), o.export(), frame, _length(m))
             assert not excl
+
+
+@pytest.mark.parametrize("nc", [5, 20])
+def test_projection_conditioning_parity(gpu, nc):
+    """Fox's projection (Eqs. 64-66) in place of the sort-and-divide bins, with number
+    control: the same projected order, intervals and mixing as the oracle."""
+    _say(f"test_projection_conditioning_parity nc={nc}")
+    mesh = W.channel_mesh(20, 24, stretch=1.1 ** 8, seed=21)
+    f = W.channel_fields(mesh)
+    mo = W.model_constants()
+    ini = W.init_desc(ppe=40, bins=(nc, 1, 1), src_x=3.0, src_r=0.4, conditioning=1)
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    excl = set()
+    for n in range(6):
+        oe.step(2e-3)
+        ge.step(2e-3)
+        ro, rg = oe.control(38, 42), ge.control(38, 42)
+        assert ro == {k: rg[k] for k in ro}, (ro, rg)
+        rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+    assert not excl
+    compare_stats(ge.stats(), oe.stats())
+
+
+def test_projection_in_large_elements(gpu):
+    """The workgroup kernel's projection: 600 per element (on chip) and 2200 per element
+    (global scratch)."""
+    _say("test_projection_in_large_elements")
+    mo = W.model_constants()
+    for nx, ny, ppe in ((4, 4, 600), (4, 2, 2200)):
+        mesh = box(nx, ny, length=2.0, jitter=0.1 if ppe == 600 else 0.0)
+        f = W.uniform_fields(mesh, mean_u=(0.3, 0.1, 0.0), mean_omega=4.0)
+        ini = W.init_desc(ppe=ppe, bins=(5, 1, 1), src_x=1.0, src_r=0.5, conditioning=1)
+        og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+        frame = og.export()["frame"]
+        for n in range(3):
+            oe.step(1e-3)
+            ge.step(1e-3)
+            compare_states(ge.export(), oe.export(), frame, _length(mesh))
+        compare_stats(ge.stats(), oe.stats())
+
+
+def test_projection_and_bins_in_one_batched_ensemble(gpu):
+    """Problems of one batched ensemble may condition differently: each equals its own
+    oracle ensemble."""
+    _say("test_projection_and_bins_in_one_batched_ensemble")
+    mo = W.model_constants()
+    m0 = W.channel_mesh(12, 10, seed=7)
+    m1 = box(6, 6, length=2.0, jitter=0.2, seed=5)
+    cases = [(m0, W.channel_fields(m0), W.init_desc(ppe=40, bins=(4, 2, 2), src_x=2.0, src_r=0.4, seed=101)),
+             (m1, W.uniform_fields(m1, mean_u=(0.5, 0.2, 0.0), mean_omega=3.0),
+              W.init_desc(ppe=90, bins=(6, 1, 1), src_x=1.0, src_r=0.5, seed=202, conditioning=1))]
+    bat = gpu.Ensemble([gpu.Grid(m, f, mo) for m, f, _ in cases], [c[2] for c in cases])
+    oes = []
+    for p, (m, f, d) in enumerate(cases):
+        dd = dict(d)
+        dd["seed"] = int(d["seed"]) ^ (p << 32)
+        og = O.Grid(m, f, mo)
+        oes.append((O.Ensemble(og, dd), og.export()["frame"], m))
+    for n in range(4):
+        bat.step([1e-3, 2e-3])
+        for (o, _, _), dt in zip(oes, (1e-3, 2e-3)):
+            o.step(dt)
+    for p, (o, frame, m) in enumerate(oes):
+        rep, excl = compare_states(bat.export(problem=p), o.export(), frame, _length(m))
+        assert not excl
+        compare_stats(bat.stats(p), o.stats())
