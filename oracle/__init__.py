@@ -84,6 +84,8 @@ def lib():
         "orc_stats": (C.c_int32, [P, dp]),
         "orc_refresh_stats": (C.c_int32, [P]),
         "orc_feedback": (C.c_int32, [P, C.c_double, C.c_int32]),
+        "orc_shift_velocities": (C.c_int32, [P, dp, dp]),
+        "orc_set_grad_p": (None, [P, dp]),
         "orc_cfl_dt": (C.c_double, [P, C.c_double]),
         "orc_redistribute": (C.c_int64, [P, C.c_int32]),
         "orc_control": (C.c_int32, [P, C.c_int32, C.c_int32, i64p]),
@@ -198,6 +200,11 @@ class Grid:
                               _p(out["wall"], C.c_uint8), _p(out["wline"], C.c_double))
         return out
 
+    def set_grad_p(self, gp):
+        """Replaces the nodal mean pressure gradient field [nn, 2]."""
+        gp = np.ascontiguousarray(gp, np.float64)
+        lib().orc_set_grad_p(self.h, _p(gp, C.c_double))
+
     def bary(self, e, x, y):
         o = (C.c_double * 3)()
         lib().orc_bary(self.h, int(e), float(x), float(y), o)
@@ -288,6 +295,15 @@ class Ensemble:
         rc = lib().orc_feedback(self.h, float(alpha), int(bool(feed_rey)))
         if rc != 0:
             raise RuntimeError(f"orc_feedback: {rc}")
+
+    def shift_velocities(self, de, dn):
+        """Eq. (31) applied with per-element particle shifts de [ne, 2] and nodal shifts
+        dn [nn, 2] of the mean velocity."""
+        de = np.ascontiguousarray(de, np.float64)
+        dn = np.ascontiguousarray(dn, np.float64)
+        rc = lib().orc_shift_velocities(self.h, _p(de, C.c_double), _p(dn, C.c_double))
+        if rc != 0:
+            raise RuntimeError(f"orc_shift_velocities: {rc}")
 
     def redistribute(self, n_min: int) -> int:
         """App. B redistribution; returns the number of moves."""

@@ -1367,6 +1367,37 @@ int32_t orc_feedback(orc_ens* E, double alpha, int32_t feed_rey)
     return 0;
 }
 
+/* Mean velocity correction of Eq. (31): the particles of element e move by -de[e] in
+   their two in-plane velocity components (the element gradient of the pressure increment
+   is constant per element), and the nodal mean velocity of node n by -dn[n] where the
+   node has statistics. */
+int32_t orc_shift_velocities(orc_ens* E, const double* de, const double* dn)
+{
+    if (!E->have_stats) return ORC_E_STATE;
+    for (int64_t i = 0; i < E->n; ++i) {
+        part* P = &E->p[i];
+        if (!P->alive) continue;
+        P->u[0] -= de[2 * (int64_t)P->e];
+        P->u[1] -= de[2 * (int64_t)P->e + 1];
+    }
+    for (int64_t n = 0; n < E->g->nn; ++n) {
+        double* o = E->stats + n * NSTAT;
+        if (!(o[0] > 0.0)) continue;
+        o[1] -= dn[2 * n];
+        o[2] -= dn[2 * n + 1];
+    }
+    return 0;
+}
+
+/* replaces the nodal mean pressure gradient [nn][2] */
+void orc_set_grad_p(orc_grid* g, const double* gp)
+{
+    for (int64_t n = 0; n < g->nn; ++n) {
+        g->F[n * NF + F_GP] = gp[2 * n];
+        g->F[n * NF + F_GP + 1] = gp[2 * n + 1];
+    }
+}
+
 /* Time step of Eq. (26): CFL * min_n sqrt(A_n) / max_n ||<Z>_n||_2, A_n the average area
    of the elements around node n, <Z>_n = (<U_1>, <U_2>, <U_3>, <omega>, <psi>) the nodal
    means of the last statistics (nodes without particles are skipped).  Returns 0 when no

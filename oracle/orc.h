@@ -84,6 +84,10 @@ int32_t orc_stats(const orc_ens*, double* out);
 int32_t orc_refresh_stats(orc_ens*);
 /* statistics feedback into the grid's nodal fields (see orc.c) */
 int32_t orc_feedback(orc_ens*, double alpha, int32_t feed_rey);
+/* Eq. (31): particles of element e shift by -de[e][2], nodal mean velocities by -dn[n][2] */
+int32_t orc_shift_velocities(orc_ens*, const double* de, const double* dn);
+/* replaces the nodal mean pressure gradient [nn][2] */
+void orc_set_grad_p(orc_grid*, const double* gp);
 /* time step of Eq. (26) from the last statistics (see orc.c) */
 double orc_cfl_dt(const orc_ens*, double cfl);
 /* particle redistribution of App. B (see orc.c); returns the number of moves */
