@@ -282,6 +282,45 @@ pdf_status pdf_set_feedback(pdf_ens ens, int32_t enable, double alpha, int32_t f
 pdf_status pdf_redistribute(pdf_ens ens, int32_t problem, int32_t n_min, int64_t* moves_out,
                             void* hip_stream);
 
+/* Constants of the elliptic relaxation model, Eqs. (12)-(17) (Table 4: C1 = 1.85,
+ * C2 = 0.63, C_L = 0.134, C_eta = 72, C_v = 1.4, gamma_5 = 0.1). */
+typedef struct {
+    double C1, C2, CL, Ceta, Cv, gamma5;
+} pdf_elliptic_model;
+
+/* Elliptic relaxation, Eq. (12) (Sec. 3.2), from the ensemble's current nodal statistics
+ * (single-problem ensembles): P1 finite elements on the grid's triangles, right-hand side
+ * (1 - C1)/2 k <omega> delta_ij + k H_ijkl d<U_k>/dx_l (Eqs. 13-15; nodal velocity
+ * gradients are the averages of the element gradients around the node), L of Eqs. (16)-(17)
+ * per element from the averages of its vertices' k and epsilon (C_xi = 1 + 1.3 n_i^2 for
+ * wp_ii, 1 for the off-diagonal components, n the outward normal of the nearest no-slip wall
+ * edge), wp_ij = -4.5 eps n_i n_j at no-slip wall nodes (Eq. 59, n the normalised sum of
+ * the adjacent wall edges' outward normals) and zero off-diagonal components at free-slip
+ * nodes (Sec. 4.1.1).  The nine components are solved together by Jacobi-preconditioned
+ * conjugate gradients from zero, until every component's residual norm falls below tol
+ * times its initial one, or max_iter iterations.  wp_out (may be NULL) receives wp_ij at the
+ * nodes, [nn][9] row-major in (i, j), on the device when out_is_device, else on the host;
+ * *iters_out (may be NULL) the iterations.  Synchronises.
+ * Errors: PDF_E_INVAL (several problems, consts or tol invalid), PDF_E_STATE (a node
+ * without statistics), PDF_E_NOMEM, PDF_E_HIP. */
+pdf_status pdf_elliptic_relaxation(pdf_ens ens, const pdf_elliptic_model* consts, double tol, int32_t max_iter,
+                                   double* wp_out, int32_t out_is_device, int32_t* iters_out, void* hip_stream);
+
+/* Stabilised pressure projection, Eqs. (30)-(33) (Sec. 3.2), after a step of a single-problem
+ * ensemble: with <U>* the nodal mean velocity of the current statistics, solves
+ * (1/rho) lap dP = (div <U>* - C_p (1/rho) lap P) / dt for the increment dP (P1 finite
+ * elements, natural condition at the walls, the solution with zero nodal sum), then applies
+ * Eq. (31): every particle's in-plane velocity moves by -(dt/rho) times the gradient of dP
+ * in its element, and the nodal mean velocity of the statistics by -(dt/rho) times the
+ * average of those gradients around the node.  P (zero at the first call) accumulates dP;
+ * the nodal mean-pressure gradient used by later steps becomes the set-up field plus the
+ * nodal average of the element gradients of P.  Jacobi-preconditioned CG from zero to tol
+ * relative residual or max_iter iterations.  dp_out (may be NULL) receives dP [nn];
+ * *iters_out (may be NULL) the iterations.  Synchronises.
+ * Errors: PDF_E_INVAL, PDF_E_STATE (a node without statistics), PDF_E_NOMEM, PDF_E_HIP. */
+pdf_status pdf_pressure_projection(pdf_ens ens, double dt, double cp, double tol, int32_t max_iter, double* dp_out,
+                                   int32_t out_is_device, int32_t* iters_out, void* hip_stream);
+
 /* Time step of Eq. (26) (Sec. 3.1) for one problem from its last statistics:
  * *dt_out = cfl * min_n sqrt(A_n) / max_n ||(<U_1>, <U_2>, <U_3>, <omega>, <psi>)_n||_2, A_n the
  * average area of the elements around node n (the paper uses cfl = 0.7); nodes without

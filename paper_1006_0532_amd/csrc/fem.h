@@ -1,0 +1,98 @@
+// P1 finite-element kernels of the Eulerian solves (Sec. 3.2): elliptic relaxation
+// (Eqs. 12-17, 59) and the stabilised pressure projection (Eqs. 30-33) with the velocity
+// correction of Eq. (31).
+//
+// The operators are applied matrix-free by node gather: row n sums, over the elements
+// around n (the node->element lists of the grid), the element matrices
+// mass * M_e + L^2_e K_e built in registers from the element's frame coordinates
+// (K_e = A_e grad N_a . grad N_b, M_e = A_e (1 + delta_ab) / 12), so every row is owned by
+// one thread, the sums run in a fixed order, and no assembled matrix has to be rebuilt
+// when L^2 changes.  Vectors hold NC components per node ([nn][NC]); the components are
+// independent systems that share the element reads.
+#pragma once
+#include "pdf_impl.h"
+
+namespace pdfgpu {
+
+constexpr int FEM_RED_BLOCKS = 256;   // partial sums of the reductions
+
+struct FemOp {
+    const ElemGeo* geo;
+    const int64_t* n2e_ptr;
+    const int32_t* n2e;
+    int64_t nn;
+    double mass;          // coefficient of M_e
+    double stiff;         // coefficient of L^2_e K_e
+    const double* L2;     // [ne][4]: L^2 of wp_11, wp_22, wp_33, off-diagonal; null: 1
+    const uint16_t* fixed; // [nn] bit c: component c of the node is a Dirichlet entry (its row
+                           // gives 0); never null (an all-zero mask for none), so that the
+                           // flags are read without a branch
+};
+
+template <int NC>
+void fem_apply(const FemOp& op, const double* x, double* y, hipStream_t s);
+template <int NC>
+void fem_diag(const FemOp& op, double* d, hipStream_t s);
+// out[c] = sum_n a[n][c] b[n][c] (b null: 1), and out[NC + c] = sum_n a2[n][c] b2[n][c]
+// when a2 is given; partial holds FEM_RED_BLOCKS x 2NC values; fixed-order sums
+template <int NC>
+void fem_dot(const double* a, const double* b, const double* a2, const double* b2, int64_t nn, double* partial,
+             double* out, hipStream_t s);
+// Jacobi-preconditioned CG steps, one independent system per component, with device
+// scalars sc = [rz NC][pAp NC][rz_new NC][rr NC][alpha NC][beta NC]; Dirichlet rows keep
+// r = z = p = 0
+template <int NC>
+void fem_cg_init(const double* b, const double* Ax, const double* diag, const uint16_t* fixed, int64_t nn,
+                 double* r, double* z, double* p, hipStream_t s);
+template <int NC>
+void fem_cg_alpha(double* sc, hipStream_t s);
+template <int NC>
+void fem_cg_xr(const double* sc, const double* p, const double* Ap, const double* diag, const uint16_t* fixed,
+               int64_t nn, double* x, double* r, double* z, hipStream_t s);
+template <int NC>
+void fem_cg_beta(double* sc, hipStream_t s);
+template <int NC>
+void fem_cg_p(const double* sc, const double* z, int64_t nn, double* p, hipStream_t s);
+
+// elliptic relaxation inputs: nodal right-hand side f [nn][9] of Eq. (12) (Eqs. 13-15,
+// nodal velocity gradients as the average of the element gradients around the node),
+// Dirichlet values [nn][9] and flags [nn] (Eq. 59 at no-slip nodes, zero off-diagonals at
+// free-slip nodes), and L^2 per element [ne][4] (Eqs. 16-17)
+struct EllipticConst {
+    double C1, C2, CL, Ceta, Cv, gamma5, nu, CT;
+};
+void fem_elliptic_inputs(const ElemGeo* geo, const int64_t* n2e_ptr, const int32_t* n2e, const double* stats,
+                         int64_t nn, int64_t ne, const EllipticConst& c, const uint8_t* wkind, const double* wnrm,
+                         const double* enrm, double* f, double* xfix, uint16_t* fixed, double* L2, uint32_t* err,
+                         hipStream_t s);
+// b = mass-matrix product of f (M f) for the nine components
+void fem_mass_rhs(const FemOp& op, const double* f, double* b, hipStream_t s);
+// x = Dirichlet value where fixed, else keep x (nine components)
+void fem_set_fixed(const double* xfix, const uint16_t* fixed, int64_t nn, double* x, hipStream_t s);
+
+// pressure projection pieces
+// b_a = -(rho/dt) int N_a div <U>* - (cp/dt) (K P)_a over the elements around node a
+void fem_pressure_rhs(const FemOp& op, const double* stats, const double* P, double rho, double dt, double cp,
+                      double* b, uint32_t* err, hipStream_t s);
+// v -= sum / nn (sum given on the device)
+void fem_sub_mean(const double* sum, int64_t nn, double* v, hipStream_t s);
+// y += a
+void fem_add(const double* a, int64_t n, double* y, hipStream_t s);
+// count of nodes whose statistics (first 12 values) are not all finite -> *count (added)
+void fem_check_stats(const double* stats, int64_t nn, unsigned long long* count, hipStream_t s);
+// per element: the gradient of the nodal field q [ne][2]
+void fem_elem_grad(const ElemGeo* geo, const double* q, int64_t ne, double* g, hipStream_t s);
+// P += dP; nodal mean-pressure gradient record = gp0 + average of the element gradients of P
+// around the node; nodal mean velocity of the statistics -= (dt/rho) x average element
+// gradient of dP where the node has statistics
+void fem_pressure_update(const int64_t* n2e_ptr, const int32_t* n2e, const double* gP, const double* gdP,
+                         const double* gp0, int64_t nn, double scale, double* node, double* stats, hipStream_t s);
+// outward normal [ne][2] of the no-slip wall edge (edges [nw][4]: midpoint, outward unit
+// normal) nearest to each element centroid; zero without wall edges
+void fem_nearest_wall(const ElemGeo* geo, int64_t ne, const double* edges, int32_t nw, double period, double* enrm,
+                      hipStream_t s);
+// particles of element e: U1, U2 -= scale x gdP[e]
+template <class R>
+void fem_correct_particles(const SoaT<R>& st, const int64_t* nslots, int64_t n_ub, const double* gdP, double scale,
+                           hipStream_t s);
+}  // namespace pdfgpu

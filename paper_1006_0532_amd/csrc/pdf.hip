@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "device.h"
+#include "fem.h"
 #include "kernels.h"
 #include "pdf_impl.h"
 
@@ -552,6 +553,199 @@ pdf_status push_real(pdf_ens_s* E, void* dst, const std::vector<double>& in, hip
 }  // namespace
 
 
+
+namespace {
+
+// the grid's element and node records are shared with other ensembles: an ensemble that
+// changes its fields (statistics feedback, the Eulerian solves) works on copies
+pdf_status ensure_own_fields(pdf_ens_s* E, hipStream_t s)
+{
+    DevGrid& g = E->dg;
+    if (g.owned || g.own_fields) return PDF_OK;
+    ElemGeo* geo = nullptr;
+    double* node = nullptr;
+    pdf_status st = dalloc(&geo, g.ne);
+    if (st == PDF_OK) st = dalloc(&node, g.nn * NODE_STRIDE);
+    if (st != PDF_OK) {
+        dfree(geo);
+        return st;
+    }
+    HIP_TRY(hipMemcpyAsync(geo, g.geo, sizeof(ElemGeo) * g.ne, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(node, g.node, sizeof(double) * g.nn * NODE_STRIDE, hipMemcpyDeviceToDevice, s));
+    g.geo = geo;
+    g.node = node;
+    g.own_fields = true;
+    drop_graphs(E);   // captured steps read the old records
+    return PDF_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Eulerian solves (Sec. 3.2)
+// ---------------------------------------------------------------------------------------
+template <class T>
+pdf_status fem_alloc(T*& p, int64_t n)
+{
+    if (p) return PDF_OK;
+    return dalloc(&p, n);
+}
+
+// boundary geometry of the grid: node kinds and normals, nearest-wall normals per element
+pdf_status fem_geometry(pdf_ens_s* E, hipStream_t s)
+{
+    FemState& F = E->fem;
+    if (F.geom) return PDF_OK;
+    const pdf_grid_s* gr = E->grid;
+    const int64_t nn = gr->nn, ne = gr->ne;
+    std::vector<uint8_t> wk(nn, 0);
+    std::vector<double> nrm(2 * nn, 0.0), edges;
+    for (int64_t e = 0; e < ne; ++e) {
+        const ElemGeo& G = gr->h_geo[e];
+        for (int k = 0; k < 3; ++k) {
+            if (G.kind[k] != KIND_WALL && G.kind[k] != KIND_SLIP) continue;
+            const int a = (k + 1) % 3, b = (k + 2) % 3;
+            const double dx = G.x[b] - G.x[a], dy = G.y[b] - G.y[a];
+            const double len = std::sqrt(dx * dx + dy * dy);
+            const double ox = dy / len, oy = -dx / len;     // right of a->b: outside a CCW element
+            if (G.kind[k] == KIND_WALL) {
+                for (int v : {a, b}) {
+                    nrm[2 * G.node[v]] += len * ox;
+                    nrm[2 * G.node[v] + 1] += len * oy;
+                    wk[G.node[v]] = 2;
+                }
+                edges.insert(edges.end(), {0.5 * (G.x[a] + G.x[b]), 0.5 * (G.y[a] + G.y[b]), ox, oy});
+            } else {
+                for (int v : {a, b})
+                    if (wk[G.node[v]] == 0) wk[G.node[v]] = 1;
+            }
+        }
+    }
+    // a node on both kinds counts as no-slip
+    for (int64_t e = 0; e < ne; ++e) {
+        const ElemGeo& G = gr->h_geo[e];
+        for (int k = 0; k < 3; ++k)
+            if (G.kind[k] == KIND_WALL) wk[G.node[(k + 1) % 3]] = wk[G.node[(k + 2) % 3]] = 2;
+    }
+    for (int64_t n = 0; n < nn; ++n)
+        if (wk[n] == 2) {
+            const double l = std::sqrt(nrm[2 * n] * nrm[2 * n] + nrm[2 * n + 1] * nrm[2 * n + 1]);
+            nrm[2 * n] /= l;
+            nrm[2 * n + 1] /= l;
+        }
+    pdf_status st = fem_alloc(F.wkind, nn);
+    if (st == PDF_OK) st = fem_alloc(F.wnrm, 2 * nn);
+    if (st == PDF_OK) st = fem_alloc(F.enrm, 2 * ne);
+    if (st != PDF_OK) return st;
+    const int32_t nw = (int32_t)(edges.size() / 4);
+    double* d_edges = nullptr;
+    st = dalloc(&d_edges, 4 * (int64_t)std::max<int32_t>(nw, 1));
+    if (st != PDF_OK) return st;
+    HIP_TRY(hipMemcpyAsync(F.wkind, wk.data(), nn, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(F.wnrm, nrm.data(), sizeof(double) * 2 * nn, hipMemcpyHostToDevice, s));
+    if (nw) HIP_TRY(hipMemcpyAsync(d_edges, edges.data(), sizeof(double) * edges.size(), hipMemcpyHostToDevice, s));
+    fem_nearest_wall(E->dg.geo, ne, d_edges, nw, gr->period, F.enrm, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    dfree(d_edges);
+    F.geom = true;
+    return PDF_OK;
+}
+
+pdf_status fem_work(pdf_ens_s* E)
+{
+    FemState& F = E->fem;
+    const int64_t nn = E->dg.nn, ne = E->dg.ne;
+    pdf_status st = PDF_OK;
+    for (double** q : {&F.f, &F.xfix, &F.b, &F.x, &F.r, &F.z, &F.p, &F.Ap, &F.diag})
+        if (st == PDF_OK) st = fem_alloc(*q, 9 * nn);
+    if (st == PDF_OK) st = fem_alloc(F.fixed, nn + 1);
+    if (st == PDF_OK && !F.nofix) {
+        st = fem_alloc(F.nofix, nn + 1);
+        if (st == PDF_OK) launch_fill_i32(reinterpret_cast<int32_t*>(F.nofix), (nn + 1) / 2, 0, E->stream);
+    }
+    if (st == PDF_OK) st = fem_alloc(F.L2, 4 * ne);
+    if (st == PDF_OK) st = fem_alloc(F.sc, 6 * 9);
+    if (st == PDF_OK) st = fem_alloc(F.partial, (int64_t)FEM_RED_BLOCKS * 18);
+    return st;
+}
+
+// statistics must be defined at every node
+pdf_status fem_check(pdf_ens_s* E, hipStream_t s, const char* who)
+{
+    launch_fill_u64(E->d_scalar, 1, 0ull, s);
+    fem_check_stats(E->stats, E->dg.nn, E->d_scalar, s);
+    unsigned long long bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, E->d_scalar, sizeof(bad), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (bad) {
+        set_error(std::string(who) + ": " + std::to_string(bad) + " nodes without statistics");
+        return PDF_E_STATE;
+    }
+    return PDF_OK;
+}
+
+// Jacobi-preconditioned CG on NC independent components: x holds the Dirichlet values
+// (and zero elsewhere) on entry and the solution on return
+template <int NC>
+pdf_status fem_cg(pdf_ens_s* E, const FemOp& op, const double* b, double tol, int32_t max_iter, int32_t* iters,
+                  hipStream_t s)
+{
+    FemState& F = E->fem;
+    const int64_t nn = op.nn;
+    launch_fill_u64(reinterpret_cast<unsigned long long*>(F.sc), 6 * NC, 0ull, s);
+    fem_diag<NC>(op, F.diag, s);
+    FemOp full = op;
+    full.fixed = F.nofix;            // the initial residual includes the Dirichlet columns
+    fem_apply<NC>(full, F.x, F.Ap, s);
+    fem_cg_init<NC>(b, F.Ap, F.diag, op.fixed, nn, F.r, F.z, F.p, s);
+    fem_dot<NC>(F.r, F.z, F.r, F.r, nn, F.partial, F.sc + 2 * NC, s);
+    fem_cg_beta<NC>(F.sc, s);
+    double rr0[NC], h[2 * NC];
+    HIP_TRY(hipMemcpyAsync(rr0, F.sc + 3 * NC, sizeof(rr0), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int32_t it = 0;
+    auto done = [&](const double* rr) {
+        for (int c = 0; c < NC; ++c)
+            if (rr[c] > tol * tol * rr0[c]) return false;
+        return true;
+    };
+    if (!done(rr0)) {
+        while (it < max_iter) {
+            fem_apply<NC>(op, F.p, F.Ap, s);
+            fem_dot<NC>(F.p, F.Ap, nullptr, nullptr, nn, F.partial, F.sc + NC, s);
+            fem_cg_alpha<NC>(F.sc, s);
+            fem_cg_xr<NC>(F.sc, F.p, F.Ap, F.diag, op.fixed, nn, F.x, F.r, F.z, s);
+            fem_dot<NC>(F.r, F.z, F.r, F.r, nn, F.partial, F.sc + 2 * NC, s);
+            fem_cg_beta<NC>(F.sc, s);
+            fem_cg_p<NC>(F.sc, F.z, nn, F.p, s);
+            ++it;
+            if (it % 8 == 0 || it == max_iter) {
+                HIP_TRY(hipMemcpyAsync(h, F.sc + 2 * NC, sizeof(h), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                if (done(h + NC)) break;
+            }
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    if (iters) *iters = it;
+    return PDF_OK;
+}
+
+FemOp fem_op(pdf_ens_s* E, double mass, double stiff, const double* L2, const uint16_t* fixed)
+{
+    FemOp op{};
+    op.geo = E->dg.geo;
+    op.n2e_ptr = E->dg.n2e_ptr;
+    op.n2e = E->dg.n2e;
+    op.nn = E->dg.nn;
+    op.mass = mass;
+    op.stiff = stiff;
+    op.L2 = L2;
+    op.fixed = fixed;
+    return op;
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------------------------------
 // Particle redistribution (App. B).  The moves are inherently serial (each one changes the
 // counts that select the next), so the host plans them from the element counts: an ordered
@@ -755,6 +949,11 @@ pdf_status pdf_ens_destroy(pdf_ens E)
     dfree(E->fb_gn);
     dfree(E->fb_h);
     dfree(E->redist_plan);
+    FemState& F = E->fem;
+    dfree(F.wkind); dfree(F.wnrm); dfree(F.enrm); dfree(F.f); dfree(F.xfix); dfree(F.b); dfree(F.x); dfree(F.r);
+    dfree(F.z); dfree(F.p); dfree(F.Ap); dfree(F.diag); dfree(F.fixed); dfree(F.nofix); dfree(F.L2); dfree(F.sc);
+    dfree(F.partial);
+    dfree(F.P); dfree(F.gp0); dfree(F.gP); dfree(F.gdP);
     delete E;
     return PDF_OK;
 }
@@ -1041,6 +1240,109 @@ pdf_status pdf_redistribute(pdf_ens E, int32_t problem, int32_t n_min, int64_t* 
     return check_device_error(E);
 }
 
+pdf_status pdf_elliptic_relaxation(pdf_ens E, const pdf_elliptic_model* consts, double tol, int32_t max_iter,
+                                   double* wp_out, int32_t out_is_device, int32_t* iters_out, void* hip_stream)
+{
+    if (iters_out) *iters_out = 0;
+    if (!E || E->n_problems != 1 || !(tol > 0.0) || !(tol < 1.0) || max_iter < 0) {
+        set_error("pdf_elliptic_relaxation: one problem, 0 < tol < 1, max_iter >= 0");
+        return PDF_E_INVAL;
+    }
+    pdf_elliptic_model c = consts ? *consts : pdf_elliptic_model{1.85, 0.63, 0.134, 72.0, 1.4, 0.1};
+    if (!std::isfinite(c.C1) || !std::isfinite(c.C2) || !(c.CL > 0.0) || !(c.Ceta >= 0.0) || !std::isfinite(c.Cv) ||
+        !std::isfinite(c.gamma5) || !std::isfinite(c.CL) || !std::isfinite(c.Ceta)) {
+        set_error("pdf_elliptic_relaxation: invalid constants");
+        return PDF_E_INVAL;
+    }
+    HIP_TRY(hipSetDevice(E->grid->device));
+    hipStream_t s = as_stream(hip_stream);
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    E->stream = s;
+    pdf_status st = fem_geometry(E, s);
+    if (st == PDF_OK) st = fem_work(E);
+    if (st == PDF_OK) st = fem_check(E, s, "pdf_elliptic_relaxation");
+    if (st != PDF_OK) return st;
+    FemState& F = E->fem;
+    const DevGrid& g = E->dg;
+    const ModelC& m = E->grid->model;
+    EllipticConst ec{c.C1, c.C2, c.CL, c.Ceta, c.Cv, c.gamma5, m.nu, m.CT};
+    fem_elliptic_inputs(g.geo, g.n2e_ptr, g.n2e, E->stats, g.nn, g.ne, ec, F.wkind, F.wnrm, F.enrm, F.f, F.xfix,
+                        F.fixed, F.L2, E->err, s);
+    FemOp op = fem_op(E, 1.0, 1.0, F.L2, F.fixed);
+    fem_mass_rhs(op, F.f, F.b, s);
+    launch_fill_u64(reinterpret_cast<unsigned long long*>(F.x), 9 * g.nn, 0ull, s);
+    fem_set_fixed(F.xfix, F.fixed, g.nn, F.x, s);
+    st = fem_cg<9>(E, op, F.b, tol, max_iter, iters_out, s);
+    if (st != PDF_OK) return st;
+    if (wp_out) {
+        const size_t bytes = sizeof(double) * 9 * g.nn;
+        HIP_TRY(hipMemcpyAsync(wp_out, F.x, bytes, out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return check_device_error(E);
+}
+
+pdf_status pdf_pressure_projection(pdf_ens E, double dt, double cp, double tol, int32_t max_iter, double* dp_out,
+                                   int32_t out_is_device, int32_t* iters_out, void* hip_stream)
+{
+    if (iters_out) *iters_out = 0;
+    if (!E || E->n_problems != 1 || !(dt > 0.0) || !std::isfinite(dt) || !(cp >= 0.0) || !std::isfinite(cp) ||
+        !(tol > 0.0) || !(tol < 1.0) || max_iter < 0) {
+        set_error("pdf_pressure_projection: one problem, dt > 0, cp >= 0, 0 < tol < 1, max_iter >= 0");
+        return PDF_E_INVAL;
+    }
+    HIP_TRY(hipSetDevice(E->grid->device));
+    hipStream_t s = as_stream(hip_stream);
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    E->stream = s;
+    pdf_status st = ensure_own_fields(E, s);
+    if (st == PDF_OK) st = fem_work(E);
+    FemState& F = E->fem;
+    const DevGrid& g = E->dg;
+    const int64_t nn = g.nn, ne = g.ne;
+    if (st == PDF_OK) st = fem_alloc(F.P, nn);
+    if (st == PDF_OK) st = fem_alloc(F.gp0, 2 * nn);
+    if (st == PDF_OK) st = fem_alloc(F.gP, 2 * ne);
+    if (st == PDF_OK) st = fem_alloc(F.gdP, 2 * ne);
+    if (st == PDF_OK) st = fem_check(E, s, "pdf_pressure_projection");
+    if (st != PDF_OK) return st;
+    if (!F.pressure) {
+        // the set-up mean-pressure gradient is the imposed part; P starts at zero
+        launch_fill_u64(reinterpret_cast<unsigned long long*>(F.P), nn, 0ull, s);
+        HIP_TRY(hipMemcpy2DAsync(F.gp0, 2 * sizeof(double), g.node + NF_GP, NODE_STRIDE * sizeof(double),
+                                 2 * sizeof(double), nn, hipMemcpyDeviceToDevice, s));
+        F.pressure = true;
+    }
+    const double rho = E->grid->model.rho;
+    FemOp op = fem_op(E, 0.0, 1.0, nullptr, F.nofix);
+    fem_pressure_rhs(op, E->stats, F.P, rho, dt, cp, F.b, E->err, s);
+    // compatibility with the constant null space: remove the mean of the right-hand side
+    fem_dot<1>(F.b, nullptr, nullptr, nullptr, nn, F.partial, F.sc, s);
+    fem_sub_mean(F.sc, nn, F.b, s);
+    launch_fill_u64(reinterpret_cast<unsigned long long*>(F.x), nn, 0ull, s);
+    st = fem_cg<1>(E, op, F.b, tol, max_iter, iters_out, s);
+    if (st != PDF_OK) return st;
+    // the solution with zero nodal sum
+    fem_dot<1>(F.x, nullptr, nullptr, nullptr, nn, F.partial, F.sc, s);
+    fem_sub_mean(F.sc, nn, F.x, s);
+    fem_elem_grad(g.geo, F.x, ne, F.gdP, s);
+    fem_add(F.x, nn, F.P, s);
+    fem_elem_grad(g.geo, F.P, ne, F.gP, s);
+    const double scale = dt / rho;
+    fem_pressure_update(g.n2e_ptr, g.n2e, F.gP, F.gdP, F.gp0, nn, scale, E->dg.node, E->stats, s);
+    if (E->precision == PDF_MIXED)
+        fem_correct_particles<float>(cur(E).as<float>(), E->d_meta, E->n_slots_ub, F.gdP, scale, s);
+    else
+        fem_correct_particles<double>(cur(E).as<double>(), E->d_meta, E->n_slots_ub, F.gdP, scale, s);
+    if (g.node32) launch_f64_to_f32(g.node, g.node32, nn * NODE_STRIDE, s);
+    HIP_TRY(hipGetLastError());
+    if (dp_out)
+        HIP_TRY(hipMemcpyAsync(dp_out, F.x, sizeof(double) * nn,
+                               out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return check_device_error(E);
+}
+
 pdf_status pdf_control(pdf_ens E, int32_t n_min, int32_t n_max, pdf_control_report* report, void* hip_stream)
 {
     if (!E || n_min < 0 || n_max < 1 || n_max < n_min) {
@@ -1293,21 +1595,9 @@ pdf_status pdf_set_feedback(pdf_ens E, int32_t enable, double alpha, int32_t fee
     E->fb_rey = feed_rey != 0;
     if (!enable) return PDF_OK;
     DevGrid& g = E->dg;
-    if (!g.owned && !g.own_fields) {
-        // the grid's records are shared with other ensembles: feed back into copies
-        ElemGeo* geo = nullptr;
-        double* node = nullptr;
-        pdf_status st = dalloc(&geo, g.ne);
-        if (st == PDF_OK) st = dalloc(&node, g.nn * NODE_STRIDE);
-        if (st != PDF_OK) {
-            dfree(geo);
-            return st;
-        }
-        HIP_TRY(hipMemcpyAsync(geo, g.geo, sizeof(ElemGeo) * g.ne, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(node, g.node, sizeof(double) * g.nn * NODE_STRIDE, hipMemcpyDeviceToDevice, s));
-        g.geo = geo;
-        g.node = node;
-        g.own_fields = true;
+    {
+        pdf_status st = ensure_own_fields(E, s);
+        if (st != PDF_OK) return st;
     }
     if (!E->fb_gn) {
         pdf_status st = dalloc(&E->fb_gn, 6 * g.nn);

@@ -128,6 +128,23 @@ struct DevGrid {
     bool own_fields = false;         // geo and node copied for statistics feedback (one problem)
 };
 
+// Work arrays of the Eulerian solves (allocated on first use, one problem).
+struct FemState {
+    bool geom = false;
+    uint8_t* wkind = nullptr;     // [nn] 0 interior, 1 free-slip node, 2 no-slip node
+    double* wnrm = nullptr;       // [nn][2] outward wall normal of no-slip nodes
+    double* enrm = nullptr;       // [ne][2] normal of the nearest no-slip wall edge
+    double *f = nullptr, *xfix = nullptr, *b = nullptr, *x = nullptr;        // [nn][9]
+    double *r = nullptr, *z = nullptr, *p = nullptr, *Ap = nullptr, *diag = nullptr;
+    uint16_t* fixed = nullptr;    // [nn] Dirichlet bits of the nine components
+    uint16_t* nofix = nullptr;    // [nn] all zero
+    double* L2 = nullptr;         // [ne][4]
+    double* sc = nullptr;         // CG scalars [6][9]
+    double* partial = nullptr;    // reduction partials
+    bool pressure = false;        // P and gp0 set up
+    double *P = nullptr, *gp0 = nullptr, *gP = nullptr, *gdP = nullptr;       // [nn], [nn][2], [ne][2]
+};
+
 struct pdf_ens_s {
     pdf_grid grid = nullptr;         // grid of problem 0
     std::vector<pdf_grid> grids;     // grid of every problem
@@ -193,6 +210,7 @@ struct pdf_ens_s {
     std::vector<int> tiers;         // particles per lane of the wavefront tiers, ascending
     bool ctl_valid = false;     // the current buffer holds the canonical order of a pass
     bool any_proj = false;      // some problem conditions by Fox's projection
+    FemState fem;
     int32_t* redist_plan = nullptr;  // [redist_cap][4] moves of the last redistribution
     int64_t redist_cap = 0;
 };

@@ -27,7 +27,8 @@ STATUS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "HIP", -4: "MESH", -5: "CAPACIT
 # every symbol include/pdf.h declares
 EXPORTS = ["pdf_grid_create", "pdf_grid_destroy", "pdf_particles_init", "pdf_ens_destroy", "pdf_step",
            "pdf_stats", "pdf_control", "pdf_count", "pdf_particles_export", "pdf_particles_import",
-           "pdf_counters", "pdf_timing", "pdf_set_feedback", "pdf_cfl_dt", "pdf_redistribute", "pdf_get_options", "pdf_set_options", "pdf_autotune",
+           "pdf_counters", "pdf_timing", "pdf_set_feedback", "pdf_cfl_dt", "pdf_redistribute", "pdf_elliptic_relaxation",
+           "pdf_pressure_projection", "pdf_get_options", "pdf_set_options", "pdf_autotune",
            "pdf_sync",
            "pdf_last_error"]
 PDF_FP64, PDF_MIXED = 0, 1
@@ -59,6 +60,10 @@ class InitDesc(C.Structure):
                 ("src_continuous", C.c_int32), ("bins", C.c_int32 * 3), ("min_per_bin", C.c_int32),
                 ("precision", C.c_int32), ("seed", C.c_uint64), ("capacity", C.c_int64),
                 ("estimator", C.c_int32), ("conditioning", C.c_int32)]
+
+
+class EllipticModel(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("C1", "C2", "CL", "Ceta", "Cv", "gamma5")]
 
 
 class Options(C.Structure):
@@ -99,6 +104,10 @@ def load(path: str = LIB_PATH):
         "pdf_set_feedback": [vp, C.c_int32, C.c_double, C.c_int32, vp],
         "pdf_cfl_dt": [vp, C.c_int32, C.c_double, dp, vp],
         "pdf_redistribute": [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64), vp],
+        "pdf_elliptic_relaxation": [vp, C.POINTER(EllipticModel), C.c_double, C.c_int32, vp, C.c_int32,
+                                    C.POINTER(C.c_int32), vp],
+        "pdf_pressure_projection": [vp, C.c_double, C.c_double, C.c_double, C.c_int32, vp, C.c_int32,
+                                    C.POINTER(C.c_int32), vp],
         "pdf_get_options": [vp, C.POINTER(Options)],
         "pdf_set_options": [vp, C.POINTER(Options)],
         "pdf_autotune": [vp, dp, C.c_int32, vp, C.POINTER(Options), ip, dp],
@@ -287,6 +296,25 @@ class Ensemble:
         v = C.c_int64()
         _check(load().pdf_redistribute(self.h, int(problem), int(n_min), C.byref(v), C.c_void_p(self.stream)))
         return int(v.value)
+
+    def elliptic_relaxation(self, consts: dict | None = None, tol: float = 1e-12, max_iter: int = 20000):
+        """Eq. (12) from the current statistics: (wp [nn, 3, 3], CG iterations)."""
+        nn = self.grids[0].nn
+        out = np.empty((nn, 3, 3))
+        it = C.c_int32()
+        m = None if consts is None else C.byref(EllipticModel(**consts))
+        _check(load().pdf_elliptic_relaxation(self.h, m, float(tol), int(max_iter), out.ctypes.data_as(C.c_void_p), 0,
+                                              C.byref(it), C.c_void_p(self.stream)))
+        return out, int(it.value)
+
+    def pressure_projection(self, dt: float, cp: float = 1e-3, tol: float = 1e-12, max_iter: int = 50000):
+        """Eqs. (30)-(33) and (31) after a step: (dP [nn], CG iterations)."""
+        nn = self.grids[0].nn
+        out = np.empty(nn)
+        it = C.c_int32()
+        _check(load().pdf_pressure_projection(self.h, float(dt), float(cp), float(tol), int(max_iter),
+                                              out.ctypes.data_as(C.c_void_p), 0, C.byref(it), C.c_void_p(self.stream)))
+        return out, int(it.value)
 
     def options(self) -> dict:
         o = Options()

@@ -1,0 +1,86 @@
+"""GPU parity of the Eulerian solves (Sec. 3.2) with the oracle's direct sparse solves:
+elliptic relaxation (Eqs. 12-17, 59) from the statistics of a few steps, and the pressure
+projection (Eqs. 30-33) with the velocity correction of Eq. (31) applied to the particles,
+the nodal mean velocity and, through the mean-pressure gradient, to the following steps.
+Tolerance: the CG stops at a relative residual of 1e-13; the direct and iterative solutions
+then agree to about the condition number times that."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import fem
+from paper_1006_0532_amd import workloads as W
+from tests.common import box
+from tests.parity import compare_states, compare_stats
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "a GPU is required"
+    from paper_1006_0532_amd import pdfgpu
+    pdfgpu.load()
+    return pdfgpu
+
+
+def _pair(gpu, mesh, f, mo, ini):
+    og = O.Grid(mesh, f, mo)
+    oe = O.Ensemble(og, ini)
+    gg = gpu.Grid(mesh, f, mo)
+    ge = gpu.Ensemble(gg, ini)
+    return og, oe, gg, ge
+
+
+def _cases():
+    m0 = W.channel_mesh(16, 20, stretch=1.1 ** 8, seed=21)
+    m1 = W.cavity_mesh(6, 8, 8, seed=9)
+    return [("channel", m0, W.channel_fields(m0), W.init_desc(ppe=60, src_x=3.0, src_r=0.4)),
+            ("cavity", m1, W.cavity_fields(m1), W.init_desc(ppe=60, src_x=1.5, src_y=0.5, src_r=0.2))]
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_elliptic_relaxation_parity(gpu, case):
+    name, mesh, f, ini = _cases()[case]
+    _say(f"test_elliptic_relaxation_parity {name}")
+    mo = W.model_constants()
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    for n in range(3):
+        oe.step(1e-3)
+        ge.step(1e-3)
+    wp, it = ge.elliptic_relaxation(tol=1e-13)
+    ex = og.export()
+    ref = fem.elliptic_relaxation(mesh, ex["frame"], ex["area"], oe.stats(), mo)
+    scale = np.abs(ref).max()
+    assert 0 < it < 20000
+    assert np.abs(wp - ref).max() <= 1e-8 * scale, (np.abs(wp - ref).max(), scale)
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_pressure_projection_parity(gpu, case):
+    name, mesh, f, ini = _cases()[case]
+    _say(f"test_pressure_projection_parity {name}")
+    mo = W.model_constants()
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    proj = fem.Projection(mesh, og, f.grad_p)
+    length = mesh.period_x
+    excl = set()
+    for n in range(3):
+        oe.step(1e-3)
+        ge.step(1e-3)
+        dpo = proj.apply(oe, 1e-3, cp=1e-3, rho=mo["rho"])
+        dpg, it = ge.pressure_projection(1e-3, cp=1e-3, tol=1e-13)
+        assert 0 < it < 50000
+        assert np.abs(dpg - dpo).max() <= 1e-8 * np.abs(dpo).max(), (n, np.abs(dpg - dpo).max())
+        rep, excl = compare_states(ge.export(), oe.export(), frame, length, excl)
+        compare_stats(ge.stats(), oe.stats())
+    assert len(excl) <= 2
