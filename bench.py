@@ -77,6 +77,8 @@ def parse():
     p.add_argument("--no-forms", action="store_true",
                    help="skip the mixed-precision and batched measurements")
     p.add_argument("--form-steps", type=int, default=10)
+    p.add_argument("--no-eulerian", action="store_true",
+                   help="skip timing the elliptic-relaxation and pressure-projection solves")
     p.add_argument("--batched-problems", type=int, default=64)
     return p.parse_args()
 
@@ -317,6 +319,22 @@ def main():
             per_kernel[k]["GB/s"] = round(bpp * mean_live / (avg * 1e-3) / 1e9, 1)
     print(f"[bench] per kernel: {json.dumps(per_kernel)}", file=sys.stderr, flush=True)
 
+    # Eulerian solves of Sec. 3.2 on the same ensemble after the timed steps (a first call
+    # sets up the boundary geometry and work arrays; the second is timed, results copied to
+    # the host included)
+    eulerian = None
+    if not args.no_eulerian:
+        eulerian = {}
+        for name, fn in (("elliptic_relaxation", lambda: ens.elliptic_relaxation(tol=1e-10)),
+                         ("pressure_projection", lambda: ens.pressure_projection(dt, cp=1e-3, tol=1e-10))):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, it = fn()
+            torch.cuda.synchronize()
+            eulerian[name] = {"ms": round(1e3 * (time.perf_counter() - t), 2), "cg_iterations": it, "tol": 1e-10}
+        print(f"[bench] eulerian: {json.dumps(eulerian)}", file=sys.stderr, flush=True)
+
     forms = None
     if not args.no_forms:
         forms = {"fp64": {"value": value, "ms_per_step": 1e3 * elapsed / args.steps}}
@@ -344,7 +362,7 @@ def main():
                    "particles": n0, "ppe": args.ppe, "dt": dt, "control": list(ctl),
                    "bins": [4, 2, 2], "precision": "fp64", "parallelism": "single GPU"},
         "roofline": roof, "rooflines": rooflines, "per_kernel": per_kernel, "cpu_baseline": cpu,
-        "forms": forms,
+        "forms": forms, "eulerian": eulerian,
     }
     print(json.dumps(out), flush=True)
 

@@ -28,6 +28,7 @@ struct AdvanceArgs {
     uint32_t* err;
     unsigned long long* cnt;    // [problem][NCOUNT][CNT_SLOTS]
     const int64_t* meta;        // [0] used slots, [4] step counter
+    int32_t* arrival;           // [cap] rank of each particle among its new host's arrivals
     int32_t* wall_list;         // [cap] slots that take a new frequency (no-slip events)
     int32_t* wall_count;
     int64_t ne;
@@ -135,6 +136,9 @@ int64_t scan_max_elems();
 void launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* tmp, hipStream_t s);
 void launch_scatter(const int32_t* elem, const int64_t* nslots, int64_t n_ub, int64_t ne, int32_t* counts,
                     const int32_t* start, int32_t* idx, uint32_t* err, hipStream_t s);
+// idx[start[elem[i]] + arrival[i]] = i for the used slots (arrival ranks from the particle loop)
+void launch_place(const int32_t* elem, const int32_t* arrival, const int64_t* nslots, int64_t n_ub, int64_t ne,
+                  const int32_t* start, int32_t* idx, uint32_t* err, hipStream_t s);
 void launch_tm(const ElemGeo* geo, const double* node, int64_t ne, const ProbParams* prm, double* tm,
                hipStream_t s);
 void launch_ctl_finish(int64_t* meta, const int32_t* off, int64_t ne, const unsigned long long* rep, int64_t cap,

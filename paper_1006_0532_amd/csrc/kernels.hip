@@ -351,13 +351,22 @@ __device__ __forceinline__ void flush_events(unsigned long long* __restrict__ cn
         if (own[q]) atomicAdd(cnt + ((int64_t)prob * NCOUNT + q) * CNT_SLOTS + slot, (unsigned long long)own[q]);
 }
 
-// particles per new host element: runs of equal keys among the lanes share one atomic
-__device__ __forceinline__ void count_new_hosts(int32_t* __restrict__ counts, int32_t key)
+// particles per new host element: runs of equal keys among the lanes share one atomic,
+// whose return value plus the lane's place in its run is the particle's arrival rank in
+// the element (its offset in the element's segment of the grouped order)
+struct HostCount {
+    int leader, rank, base;
+};
+__device__ __forceinline__ HostCount count_new_hosts(int32_t* __restrict__ counts, int32_t key)
 {
-    int leader, len, rank;
-    wave_runs(key, leader, len, rank);
-    if (rank == 0 && key >= 0) atomicAdd(counts + key, len);
+    HostCount h;
+    int len;
+    wave_runs(key, h.leader, len, h.rank);
+    h.base = 0;
+    if (h.rank == 0 && key >= 0) h.base = atomicAdd(counts + key, len);
+    return h;
 }
+__device__ __forceinline__ int arrival_rank(const HostCount& h) { return __shfl(h.base, h.leader) + h.rank; }
 
 // Particle loop: one thread per used slot (merged particles are dead slots, elem < 0)
 template <class R, bool BATCHED>
@@ -386,8 +395,11 @@ __device__ __forceinline__ void particle_loop(const AdvanceArgs<R>& a)
         base = __shfl(base, 0);
         if (ev.resample) a.wall_list[base + __popcll(rm & ((1ull << lane) - 1ull))] = (int32_t)i;
     }
-    count_new_hosts(a.counts, key);
+    // the counting atomic is in flight while the event counters are flushed
+    const HostCount hc = count_new_hosts(a.counts, key);
     flush_events<BATCHED>(a.cnt, ev, prob);
+    const int arrival = arrival_rank(hc);
+    if (key >= 0) a.arrival[i] = arrival;
 }
 
 // One problem: three wavefronts per SIMD (at most 168 registers; the FP64 form spills a
@@ -562,6 +574,23 @@ __global__ void __launch_bounds__(256) k_scatter(const int32_t* __restrict__ ele
             else atomicOr(err, ERR_BADELEM);
         }
     }
+}
+
+// Slot of every live particle inside its element's segment from the arrival ranks of the
+// particle loop (no atomics); the counts are cleared separately.
+__global__ void __launch_bounds__(256) k_place(const int32_t* __restrict__ elem, const int32_t* __restrict__ arrival,
+                                               const int64_t* __restrict__ nslots, int64_t n_ub, int64_t ne,
+                                               const int32_t* __restrict__ start, int32_t* __restrict__ idx,
+                                               uint32_t* __restrict__ err)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_ub || i >= *nslots) return;
+    const int32_t e = elem[i];
+    if (e < 0 || e >= ne) return;
+    const int64_t lo = start[e], hi = start[e + 1];
+    const int64_t slot = lo + (int64_t)arrival[i];
+    if (slot >= lo && slot < hi) idx[slot] = (int32_t)i;
+    else atomicOr(err, ERR_BADELEM);
 }
 
 // =====================================================================================
@@ -1855,6 +1884,13 @@ void launch_scatter(const int32_t* elem, const int64_t* nslots, int64_t n_ub, in
 {
     if (n_ub > 0)
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n_ub, 256 * SCAT_ROUNDS)), dim3(256), 0, s, elem, nslots, ne, counts,
+                           start, idx, err);
+}
+void launch_place(const int32_t* elem, const int32_t* arrival, const int64_t* nslots, int64_t n_ub, int64_t ne,
+                  const int32_t* start, int32_t* idx, uint32_t* err, hipStream_t s)
+{
+    if (n_ub > 0)
+        hipLaunchKernelGGL(k_place, dim3(blocks_for(n_ub, 256)), dim3(256), 0, s, elem, arrival, nslots, n_ub, ne,
                            start, idx, err);
 }
 template <class R>

@@ -129,7 +129,12 @@ pdf_status regroup(pdf_ens_s* E, bool mix, bool counts_ready, bool advance_step,
         Timed t(E, T_SCAN, s);
         launch_scan(E->counts, g.ne, E->start, E->scan_tmp, s);
     }
-    {
+    if (counts_ready) {
+        // the particle loop left every particle's arrival rank: place without atomics
+        Timed t(E, T_SCATTER, s);
+        launch_fill_i32(E->counts, g.ne, 0, s);
+        launch_place(in.elem, E->arrival, E->d_meta, E->n_slots_ub, g.ne, E->start, E->idx, E->err, s);
+    } else {
         Timed t(E, T_SCATTER, s);
         launch_scatter(in.elem, E->d_meta, E->n_slots_ub, g.ne, E->counts, E->start, E->idx, E->err, s);
     }
@@ -210,6 +215,7 @@ pdf_status step_once(pdf_ens_s* E, hipStream_t s)
     a.err = E->err;
     a.cnt = E->cnt;
     a.meta = E->d_meta;
+    a.arrival = E->arrival;
     a.wall_list = E->idx;          // free between the particle loop and the scatter
     a.wall_count = E->big_count + 1;
     a.ne = g.ne;
@@ -941,7 +947,7 @@ pdf_status pdf_ens_destroy(pdf_ens E)
         dfree(S.x); dfree(S.y); free_raw(S.u0); free_raw(S.u1); free_raw(S.u2); free_raw(S.om); free_raw(S.psi);
         free_raw(S.w); dfree(S.pid); dfree(S.elem);
     }
-    dfree(E->counts); dfree(E->start); dfree(E->idx); dfree(E->scan_tmp); dfree(E->d_meta); free_raw(E->part);
+    dfree(E->counts); dfree(E->start); dfree(E->idx); dfree(E->arrival); dfree(E->scan_tmp); dfree(E->d_meta); free_raw(E->part);
     dfree(E->stats); free_raw(E->shift); dfree(E->tm); dfree(E->err); dfree(E->cnt); dfree(E->gkey); dfree(E->gord);
     dfree(E->gu3); dfree(E->ctl_clone); dfree(E->ctl_off); dfree(E->ctl_rep); dfree(E->big_list);
     dfree(E->big_count); dfree(E->d_prm); dfree(E->d_scalar);
@@ -1072,6 +1078,7 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
     if (st == PDF_OK) st = dalloc(&E->counts, g.ne);
     if (st == PDF_OK) st = dalloc(&E->start, g.ne + 1);
     if (st == PDF_OK) st = dalloc(&E->idx, cap);
+    if (st == PDF_OK) st = dalloc(&E->arrival, cap);
     if (st == PDF_OK) st = dalloc(&E->scan_tmp, scan_blocks(g.ne) + 1);
     if (st == PDF_OK) st = dalloc(&E->d_meta, 8);
     if (st == PDF_OK) st = alloc_raw(&E->part, g.ne * 3 * NPART, rs);

@@ -165,6 +165,7 @@ struct pdf_ens_s {
     int32_t* counts = nullptr;   // [ne] particles per element (zero between steps)
     int32_t* start = nullptr;    // [ne+1] segment starts of the current buffer
     int32_t* idx = nullptr;      // [cap] slot of each grouped particle
+    int32_t* arrival = nullptr;  // [cap] arrival rank of each slot in its new host (particle loop)
     int32_t* scan_tmp = nullptr; // block sums
     int64_t* d_meta = nullptr;   // [0] used slots, [1] live, [2] clones of the last control, [4] step
     void* part = nullptr;        // [ne][3][NPART] per-vertex partial sums (state precision)
