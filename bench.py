@@ -32,16 +32,16 @@ VALU_OPS_PER_PARTICLE = {"advance": 1000}
 # algorithmic HBM bytes per live particle (FP64 state): what each kernel must read and
 # write once
 BYTES_PER_PARTICLE = {
-    # read x, y, U(3), omega, pid, elem; write x, y, U(3), omega, elem
-    "advance": 6 * 8 + 8 + 4 + 6 * 8 + 4,
+    # read x, y, U(3), omega, pid, elem; write x, y, U(3), omega, elem and the arrival rank
+    "advance": 6 * 8 + 8 + 4 + 6 * 8 + 4 + 4,
     # read idx, U(3), pid, x, y, omega, psi, w; write the 10 state arrays in canonical order
     "element_pass": 4 + 4 * 8 + 5 * 8 + (8 * 8 + 8 + 4),
-    # read elem, write idx
-    "scatter": 4 + 4,
+    # placement in the grouped order: read elem and arrival rank, write idx
+    "scatter": 4 + 4 + 4,
 }
 
 
-KERNEL_NAMES = {"advance": "k_advance", "element_pass": "k_element_wave", "scatter": "k_scatter"}
+KERNEL_NAMES = {"advance": "k_advance", "element_pass": "k_element_wave", "scatter": "k_place"}
 COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_channel_large.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1006_0532_amd", "csrc", "kernels.hip")
 
