@@ -86,6 +86,7 @@ def lib():
         "orc_feedback": (C.c_int32, [P, C.c_double, C.c_int32]),
         "orc_shift_velocities": (C.c_int32, [P, dp, dp]),
         "orc_set_grad_p": (None, [P, dp]),
+        "orc_set_wp": (None, [P, dp]),
         "orc_cfl_dt": (C.c_double, [P, C.c_double]),
         "orc_redistribute": (C.c_int64, [P, C.c_int32]),
         "orc_control": (C.c_int32, [P, C.c_int32, C.c_int32, i64p]),
@@ -205,6 +206,11 @@ class Grid:
         gp = np.ascontiguousarray(gp, np.float64)
         lib().orc_set_grad_p(self.h, _p(gp, C.c_double))
 
+    def set_wp(self, wp):
+        """Replaces the nodal elliptic-relaxation tensor, wp [nn, 3, 3]."""
+        wp = np.ascontiguousarray(wp, np.float64)
+        lib().orc_set_wp(self.h, _p(wp, C.c_double))
+
     def bary(self, e, x, y):
         o = (C.c_double * 3)()
         lib().orc_bary(self.h, int(e), float(x), float(y), o)
@@ -288,11 +294,11 @@ class Ensemble:
             raise RuntimeError(f"oracle stats failed: {rc}")
         return out
 
-    def feedback(self, alpha: float, feed_rey: bool = False):
+    def feedback(self, alpha: float, feed_rey: bool = False, feed_omega: bool = False):
         """Nodal statistics of the last step become the grid's fields (mean velocity scaled
-        by alpha, Reynolds stresses when feed_rey); gradients and Laplacians are derived
-        again.  The grid is modified."""
-        rc = lib().orc_feedback(self.h, float(alpha), int(bool(feed_rey)))
+        by alpha, Reynolds stresses when feed_rey, mean frequency when feed_omega);
+        gradients and Laplacians are derived again.  The grid is modified."""
+        rc = lib().orc_feedback(self.h, float(alpha), int(bool(feed_rey)) | (2 if feed_omega else 0))
         if rc != 0:
             raise RuntimeError(f"orc_feedback: {rc}")
 

@@ -30,8 +30,10 @@
 #endif
 
 /* nodal field record: grad<P>(2), wp(6), <U>(3), lap<U>(3), <omega>(1), R(6) */
-#define NF 21
-enum { F_GP = 0, F_WP = 2, F_MU = 8, F_LAP = 11, F_OM = 14, F_RE = 15 };
+#define NF 24
+/* nodal fields: grad<P> (2), wp_11, wp_22, wp_33, wp_12, wp_13, wp_23 (6), <U> (3),
+   lap<U> (3), <omega>, R (6), wp_21, wp_31, wp_32 (3: wp is not symmetric, Eq. 13) */
+enum { F_GP = 0, F_WP = 2, F_MU = 8, F_LAP = 11, F_OM = 14, F_RE = 15, F_WPT = 21 };
 enum { TAG_INIT = 1, TAG_STEP = 2, TAG_WALL_GAMMA = 3, TAG_INIT_GAMMA = 4 };
 enum { K_INTERIOR = 0, K_WALL = 1, K_SLIP = 2, K_PERIODIC = 3 };
 #define MAX_WALK 64
@@ -393,6 +395,7 @@ orc_grid* orc_grid_create(int64_t nn, const double* xy, int64_t ne, const int32_
         double* f = g->F + n * NF;
         f[F_GP] = grad_p[2 * n]; f[F_GP + 1] = grad_p[2 * n + 1];
         for (int q = 0; q < 6; ++q) f[F_WP + q] = wp[6 * n + q];
+        for (int q = 0; q < 3; ++q) f[F_WPT + q] = wp[6 * n + 3 + q];     /* symmetric input */
         for (int q = 0; q < 3; ++q) f[F_MU + q] = mean_u[3 * n + q];
         f[F_OM] = mean_omega[n];
         for (int q = 0; q < 6; ++q) f[F_RE + q] = rey[6 * n + q];
@@ -596,19 +599,20 @@ static int advance_one(const orc_ens* E, part* p, double dt, counters* cn)
     const double R12 = f[F_RE + 3], R13 = f[F_RE + 4], R23 = f[F_RE + 5];
     const double W11 = f[F_WP], W22 = f[F_WP + 1], W33 = f[F_WP + 2];
     const double W12 = f[F_WP + 3], W13 = f[F_WP + 4], W23 = f[F_WP + 5];
+    const double W21 = f[F_WPT], W31 = f[F_WPT + 1], W32 = f[F_WPT + 2];
 
     double k = 0.5 * (R11 + R22 + R33);                       /* k = <u_i u_i>/2 */
     double Om = f[F_OM];
     double eps = Om * (k + m->nu * m->CT * m->CT * Om);          /* Eq. (18) */
-    double wpR = W11 * R11 + W22 * R22 + W33 * R33 + 2.0 * (W12 * R12 + W13 * R13 + W23 * R23);
+    double wpR = W11 * R11 + W22 * R22 + W33 * R33 + ((W12 + W21) * R12 + (W13 + W31) * R13 + (W23 + W32) * R23);
     double c0eps = -2.0 * wpR / (3.0 * k);                     /* C0*eps from Eq. (11) */
     if (c0eps < 0.0) { c0eps = 0.0; cn->c[5]++; }
     /* production P = -<u_i u_j> d<U_i>/dx_j, j over the two resolved directions */
     double prod = -(R11 * gu[0] + R12 * gu[1] + R12 * gu[2] + R22 * gu[3] + R13 * gu[4] + R23 * gu[5]);
     double Sw = m->Cw2 - m->Cw1 * prod / eps;                  /* Eq. (20) */
     double G[3][3] = { { (W11 - 0.5 * eps) / k, W12 / k, W13 / k },
-                       { W12 / k, (W22 - 0.5 * eps) / k, W23 / k },
-                       { W13 / k, W23 / k, (W33 - 0.5 * eps) / k } };   /* Eq. (11) */
+                       { W21 / k, (W22 - 0.5 * eps) / k, W23 / k },
+                       { W31 / k, W32 / k, (W33 - 0.5 * eps) / k } };   /* Eq. (11) */
 
     /* 6 Gaussians and one uniform per particle and step (Sec. 3.9) */
     uint32_t w[8];
@@ -1347,7 +1351,8 @@ int32_t orc_control(orc_ens* E, int32_t n_min, int32_t n_max, int64_t* report)
 /* Statistics feedback (Sec. 3.1, Table 1: a time step uses the Eulerian statistics of the
    step before).  The nodal mean velocity of the last statistics, scaled by alpha (the
    alpha of Eq. 47 in the redistribution test of Sec. 3.7), becomes the nodal <U> field;
-   with feed_rey the Reynolds stresses become the nodal R field where their trace is
+   with bit 0 of feed the Reynolds stresses become the nodal R field where their trace is
+   positive, with bit 1 the mean frequency becomes the nodal <omega> where it is
    positive.  Nodes without particles (W = 0) keep their fields.  Element gradients and
    Laplacians are derived again from the new <U>.  The micromixing time scale keeps its
    set-up value. */
@@ -1360,8 +1365,9 @@ int32_t orc_feedback(orc_ens* E, double alpha, int32_t feed_rey)
         double* f = g->F + n * NF;
         if (!(o[0] > 0.0)) continue;
         for (int q = 0; q < 3; ++q) f[F_MU + q] = alpha * o[1 + q];
-        if (feed_rey && o[6] + o[7] + o[8] > 0.0)
+        if ((feed_rey & 1) && o[6] + o[7] + o[8] > 0.0)
             for (int q = 0; q < 6; ++q) f[F_RE + q] = o[6 + q];
+        if ((feed_rey & 2) && o[4] > 0.0) f[F_OM] = o[4];
     }
     derive_fields(g);
     return 0;
@@ -1387,6 +1393,18 @@ int32_t orc_shift_velocities(orc_ens* E, const double* de, const double* dn)
         o[2] -= dn[2 * n + 1];
     }
     return 0;
+}
+
+/* replaces the nodal elliptic-relaxation tensor by wp [nn][3][3] (row-major ij) */
+void orc_set_wp(orc_grid* g, const double* wp)
+{
+    for (int64_t n = 0; n < g->nn; ++n) {
+        const double* w = wp + 9 * n;
+        double* f = g->F + n * NF;
+        f[F_WP] = w[0]; f[F_WP + 1] = w[4]; f[F_WP + 2] = w[8];
+        f[F_WP + 3] = w[1]; f[F_WP + 4] = w[2]; f[F_WP + 5] = w[5];
+        f[F_WPT] = w[3]; f[F_WPT + 1] = w[6]; f[F_WPT + 2] = w[7];
+    }
 }
 
 /* replaces the nodal mean pressure gradient [nn][2] */

@@ -88,6 +88,8 @@ int32_t orc_feedback(orc_ens*, double alpha, int32_t feed_rey);
 int32_t orc_shift_velocities(orc_ens*, const double* de, const double* dn);
 /* replaces the nodal mean pressure gradient [nn][2] */
 void orc_set_grad_p(orc_grid*, const double* gp);
+/* replaces the nodal elliptic-relaxation tensor, wp [nn][3][3] row-major */
+void orc_set_wp(orc_grid*, const double* wp);
 /* time step of Eq. (26) from the last statistics (see orc.c) */
 double orc_cfl_dt(const orc_ens*, double cfl);
 /* particle redistribution of App. B (see orc.c); returns the number of moves */
