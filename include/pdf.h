@@ -256,13 +256,14 @@ pdf_status pdf_timing(pdf_ens ens, int32_t enable, double* ms_out, int64_t* laun
 /* Statistics feedback (Sec. 3.1, Table 1 order: a step uses the Eulerian statistics of the
  * step before).  enable != 0: the nodal mean velocity of the current statistics, scaled
  * by alpha (the alpha of Eq. 47 in the redistribution test of Sec. 3.7; 1 for plain
- * feedback), and with feed_rey the Reynolds stresses (where their trace is positive)
- * become the ensemble's nodal <U> and R fields, now and after every later step; element
+ * feedback), with bit 0 of feed the Reynolds stresses (where their trace is positive) and
+ * with bit 1 the mean frequency (where positive) become the ensemble's nodal <U>, R and
+ * <omega> fields, now and after every later step; element
  * gradients (Eq. 40) and nodal Laplacians (Sec. 3.4) of <U> are derived again.  Nodes
  * without particles keep their fields; the micromixing time scale keeps its set-up value.
  * The ensemble works on its own copy of the fields (the grid is not modified).
  * enable = 0 stops the feedback and keeps the current fields.  Synchronises. */
-pdf_status pdf_set_feedback(pdf_ens ens, int32_t enable, double alpha, int32_t feed_rey, void* hip_stream);
+pdf_status pdf_set_feedback(pdf_ens ens, int32_t enable, double alpha, int32_t feed, void* hip_stream);
 
 /* Particle redistribution (App. B) of one problem (problem = -1: every problem, in order)
  * on the canonical order of the last step: while the element with the fewest particles has
@@ -298,13 +299,16 @@ typedef struct {
  * the adjacent wall edges' outward normals) and zero off-diagonal components at free-slip
  * nodes (Sec. 4.1.1).  The nine components are solved together by Jacobi-preconditioned
  * conjugate gradients from zero, until every component's residual norm falls below tol
- * times its initial one, or max_iter iterations.  wp_out (may be NULL) receives wp_ij at the
- * nodes, [nn][9] row-major in (i, j), on the device when out_is_device, else on the host;
- * *iters_out (may be NULL) the iterations.  Synchronises.
+ * times its initial one, or max_iter iterations.  store != 0: the solution becomes the
+ * ensemble's nodal wp field (all nine components) for the following steps, closing the loop
+ * of Table 1 (the ensemble then works on its own copy of the fields).  wp_out (may be NULL)
+ * receives wp_ij at the nodes, [nn][9] row-major in (i, j), on the device when
+ * out_is_device, else on the host; *iters_out (may be NULL) the iterations.  Synchronises.
  * Errors: PDF_E_INVAL (several problems, consts or tol invalid), PDF_E_STATE (a node
  * without statistics), PDF_E_NOMEM, PDF_E_HIP. */
 pdf_status pdf_elliptic_relaxation(pdf_ens ens, const pdf_elliptic_model* consts, double tol, int32_t max_iter,
-                                   double* wp_out, int32_t out_is_device, int32_t* iters_out, void* hip_stream);
+                                   int32_t store, double* wp_out, int32_t out_is_device, int32_t* iters_out,
+                                   void* hip_stream);
 
 /* Stabilised pressure projection, Eqs. (30)-(33) (Sec. 3.2), after a step of a single-problem
  * ensemble: with <U>* the nodal mean velocity of the current statistics, solves
@@ -314,7 +318,8 @@ pdf_status pdf_elliptic_relaxation(pdf_ens ens, const pdf_elliptic_model* consts
  * in its element, and the nodal mean velocity of the statistics by -(dt/rho) times the
  * average of those gradients around the node.  P (zero at the first call) accumulates dP;
  * the nodal mean-pressure gradient used by later steps becomes the set-up field plus the
- * nodal average of the element gradients of P.  Jacobi-preconditioned CG from zero to tol
+ * nodal average of the element gradients of P; with statistics feedback on, the corrected
+ * nodal mean velocity is fed back again.  Jacobi-preconditioned CG from zero to tol
  * relative residual or max_iter iterations.  dp_out (may be NULL) receives dP [nn];
  * *iters_out (may be NULL) the iterations.  Synchronises.
  * Errors: PDF_E_INVAL, PDF_E_STATE (a node without statistics), PDF_E_NOMEM, PDF_E_HIP. */

@@ -70,6 +70,9 @@ void fem_mass_rhs(const FemOp& op, const double* f, double* b, hipStream_t s);
 // x = Dirichlet value where fixed, else keep x (nine components)
 void fem_set_fixed(const double* xfix, const uint16_t* fixed, int64_t nn, double* x, hipStream_t s);
 
+// nodal wp records (nine components) from the solution [nn][9] (row-major ij)
+void fem_store_wp(const double* wp9, int64_t nn, double* node, hipStream_t s);
+
 // pressure projection pieces
 // b_a = -(rho/dt) int N_a div <U>* - (cp/dt) (K P)_a over the elements around node a
 void fem_pressure_rhs(const FemOp& op, const double* stats, const double* P, double rho, double dt, double cp,

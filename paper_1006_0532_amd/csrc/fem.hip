@@ -443,7 +443,30 @@ __global__ void __launch_bounds__(256) k_fem_nearest_wall(const ElemGeo* __restr
     enrm[2 * e + 1] = jb >= 0 ? edges[4 * jb + 3] : 0.0;
 }
 
+__global__ void __launch_bounds__(256) k_fem_store_wp(const double* __restrict__ x, int64_t nn,
+                                                      double* __restrict__ node)
+{
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= nn) return;
+    const double* w = x + 9 * n;
+    double* f = node + n * NODE_STRIDE;
+    f[NF_WP] = w[0];
+    f[NF_WP + 1] = w[4];
+    f[NF_WP + 2] = w[8];
+    f[NF_WP + 3] = w[1];
+    f[NF_WP + 4] = w[2];
+    f[NF_WP + 5] = w[5];
+    f[NF_WPT] = w[3];
+    f[NF_WPT + 1] = w[6];
+    f[NF_WPT + 2] = w[7];
+}
+
 }  // namespace
+
+void fem_store_wp(const double* wp9, int64_t nn, double* node, hipStream_t s)
+{
+    if (nn > 0) hipLaunchKernelGGL(k_fem_store_wp, dim3(blocks(nn, 256)), dim3(256), 0, s, wp9, nn, node);
+}
 
 void fem_nearest_wall(const ElemGeo* geo, int64_t ne, const double* edges, int32_t nw, double period, double* enrm,
                       hipStream_t s)

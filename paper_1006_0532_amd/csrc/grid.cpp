@@ -147,6 +147,7 @@ pdf_status build_grid(pdf_grid_s& g, const pdf_mesh_desc& m, const pdf_fields_de
         r[NF_GP] = f.grad_p[2 * n];
         r[NF_GP + 1] = f.grad_p[2 * n + 1];
         for (int q = 0; q < 6; ++q) r[NF_WP + q] = f.wp[6 * n + q];
+        for (int q = 0; q < 3; ++q) r[NF_WPT + q] = f.wp[6 * n + 3 + q];   // symmetric input
         for (int q = 0; q < 3; ++q) r[NF_MU + q] = f.mean_u[3 * n + q];
         r[NF_OM] = f.mean_omega[n];
         for (int q = 0; q < 6; ++q) r[NF_RE + q] = f.rey[6 * n + q];

@@ -101,8 +101,9 @@ struct ControlArgs {
     int32_t n_min, n_max;
 };
 
+// wp_full: the nodal wp field has nine components (else symmetric: six are read)
 template <class R>
-void launch_advance(const AdvanceArgs<R>& a, int64_t n_ub, bool batched, int block, hipStream_t s);
+void launch_advance(const AdvanceArgs<R>& a, int64_t n_ub, bool batched, bool wp_full, int block, hipStream_t s);
 // wavefront tiers of increasing capacity 64 x tiers[t], then the workgroup kernel
 template <class R>
 void launch_element_pass(const ElementArgs<R>& a, const int* tiers, int n_tiers, hipStream_t s);

@@ -56,7 +56,9 @@ struct AdvEvents {
 // One particle of the particle loop.  Returns its new host element (its old one when it
 // could not be tracked) and the particle's problem in prob.  R = double: FP64 throughout;
 // R = float: velocity, frequency and their SDEs in FP32, positions and tracking in FP64.
-template <class R, bool BATCHED>
+// WPFULL: the nodal wp field has all nine components (stored by the elliptic-relaxation
+// solve); otherwise it is symmetric and the three lower components are not read
+template <class R, bool BATCHED, bool WPFULL>
 __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const int64_t i, const int32_t e,
                                                const uint32_t step, AdvEvents& ev, int& prob)
 {
@@ -76,7 +78,7 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
     // The lanes of a wavefront mostly share one or two elements (particles are in
     // canonical order): loop over the distinct elements, so that element and node records
     // are wave-uniform scalar loads instead of per-lane vector loads.
-    R f[21], gu[6];
+    R f[NODE_STRIDE], gu[6];
     {
         unsigned long long todo = __ballot(true);
         while (todo) {
@@ -97,7 +99,7 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
                 const R* __restrict__ FB = a.node + (int64_t)Gu->node[1] * NODE_STRIDE;
                 const R* __restrict__ FC = a.node + (int64_t)Gu->node[2] * NODE_STRIDE;
                 // three groups of fields; the empty asm statements keep the compiler from
-                // loading all 63 node values at once.  Explicit fused multiply-adds fix the
+                // loading all 72 node values at once.  Explicit fused multiply-adds fix the
                 // rounding whatever the operands' registers.
                 auto ip = [&](int q) { return fma(lc, FC[q], fma(lb, FB[q], la * FA[q])); };
 #pragma unroll
@@ -107,7 +109,7 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
                 for (int q = 7; q < 14; ++q) f[q] = ip(q);
                 asm volatile("" ::: "memory");
 #pragma unroll
-                for (int q = 14; q < 21; ++q) f[q] = ip(q);
+                for (int q = 14; q < (WPFULL ? 24 : 21); ++q) f[q] = ip(q);
 #pragma unroll
                 for (int q = 0; q < 6; ++q) gu[q] = (R)Gu->gu[q];
             }
@@ -124,7 +126,8 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
     const R prod = -(R11 * gu0 + R12 * gu1 + R12 * gu2 + R22 * gu3 + R13 * gu4 + R23 * gu5);
     const R W11 = f[NF_WP], W22 = f[NF_WP + 1], W33 = f[NF_WP + 2];
     const R W12 = f[NF_WP + 3], W13 = f[NF_WP + 4], W23 = f[NF_WP + 5];
-    const R wpR = W11 * R11 + W22 * R22 + W33 * R33 + R(2) * (W12 * R12 + W13 * R13 + W23 * R23);
+    const R W21 = WPFULL ? f[NF_WPT] : W12, W31 = WPFULL ? f[NF_WPT + 1] : W13, W32 = WPFULL ? f[NF_WPT + 2] : W23;
+    const R wpR = W11 * R11 + W22 * R22 + W33 * R33 + ((W12 + W21) * R12 + (W13 + W31) * R13 + (W23 + W32) * R23);
     R c0eps = -R(2) * wpR / (R(3) * k);
     if (c0eps < R(0)) {
         c0eps = R(0);
@@ -134,6 +137,7 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
     const R ik = R(1) / k;
     const R G11 = (W11 - R(0.5) * eps) * ik, G22 = (W22 - R(0.5) * eps) * ik, G33 = (W33 - R(0.5) * eps) * ik;
     const R G12 = W12 * ik, G13 = W13 * ik, G23 = W23 * ik;
+    const R G21 = W21 * ik, G31 = W31 * ik, G32 = W32 * ik;
 
     // random numbers: 6 Gaussians and one uniform (Sec. 3.9)
     const Words4 wA = rng_draw(P.key, pid, step, TAG_STEP, 0);
@@ -152,8 +156,8 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
     const R d0 = u0 - f[NF_MU], d1 = u1 - f[NF_MU + 1], d2 = u2 - f[NF_MU + 2];
     const R irho = R(1) / rho;
     const R dr0 = -f[NF_GP] * irho + R(2) * nu * f[NF_LAP] + G11 * d0 + G12 * d1 + G13 * d2;
-    const R dr1 = -f[NF_GP + 1] * irho + R(2) * nu * f[NF_LAP + 1] + G12 * d0 + G22 * d1 + G23 * d2;
-    const R dr2 = R(2) * nu * f[NF_LAP + 2] + G13 * d0 + G23 * d1 + G33 * d2;
+    const R dr1 = -f[NF_GP + 1] * irho + R(2) * nu * f[NF_LAP + 1] + G21 * d0 + G22 * d1 + G23 * d2;
+    const R dr2 = R(2) * nu * f[NF_LAP + 2] + G31 * d0 + G32 * d1 + G33 * d2;
     R v0 = u0 + dr0 * dt + s2nu * (gu0 * dWx + gu1 * dWy) + sc0 * dWp0;
     R v1 = u1 + dr1 * dt + s2nu * (gu2 * dWx + gu3 * dWy) + sc0 * dWp1;
     R v2 = u2 + dr2 * dt + s2nu * (gu4 * dWx + gu5 * dWy) + sc0 * dWp2;
@@ -369,7 +373,7 @@ __device__ __forceinline__ HostCount count_new_hosts(int32_t* __restrict__ count
 __device__ __forceinline__ int arrival_rank(const HostCount& h) { return __shfl(h.base, h.leader) + h.rank; }
 
 // Particle loop: one thread per used slot (merged particles are dead slots, elem < 0)
-template <class R, bool BATCHED>
+template <class R, bool BATCHED, bool WPFULL>
 __device__ __forceinline__ void particle_loop(const AdvanceArgs<R>& a)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -384,7 +388,7 @@ __device__ __forceinline__ void particle_loop(const AdvanceArgs<R>& a)
             atomicOr(a.err, ERR_BADELEM);
             e = -1;
         }
-        if (e >= 0) key = advance_one<R, BATCHED>(a, i, e, step, ev, prob);
+        if (e >= 0) key = advance_one<R, BATCHED, WPFULL>(a, i, e, step, ev, prob);
     }
     // slots whose frequency is drawn again: one atomic per wavefront
     const unsigned long long rm = __ballot(ev.resample != 0);
@@ -404,17 +408,17 @@ __device__ __forceinline__ void particle_loop(const AdvanceArgs<R>& a)
 
 // One problem: three wavefronts per SIMD (at most 168 registers; the FP64 form spills a
 // few values of its cold paths).
-template <class R>
+template <class R, bool WPFULL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_advance(AdvanceArgs<R> a)
 {
-    particle_loop<R, false>(a);
+    particle_loop<R, false, WPFULL>(a);
 }
 
 // Several problems: per-particle problem parameters from the table
 template <class R>
 __global__ void __launch_bounds__(256) k_advance_batched(AdvanceArgs<R> a)
 {
-    particle_loop<R, true>(a);
+    particle_loop<R, true, false>(a);
 }
 
 // Eq. (58) for the particles of the last no-slip events: omega ~ Gamma(1/C4) with the mean
@@ -1726,6 +1730,8 @@ __global__ void __launch_bounds__(256) k_shift_init(const R* __restrict__ node, 
 // =====================================================================================
 // nodal <U> <- alpha * mean velocity; R <- Reynolds stresses (trace > 0); nodes without
 // particles keep their fields
+// rey: bit 0 feeds the Reynolds stresses (where their trace is positive), bit 1 the mean
+// frequency (where positive)
 __global__ void __launch_bounds__(256) k_fb_nodes(const double* __restrict__ stats, double* __restrict__ node,
                                                   int64_t nn, double alpha, int32_t rey)
 {
@@ -1735,8 +1741,9 @@ __global__ void __launch_bounds__(256) k_fb_nodes(const double* __restrict__ sta
     double* f = node + i * NODE_STRIDE;
     if (!(o[0] > 0.0)) return;
     for (int q = 0; q < 3; ++q) f[NF_MU + q] = alpha * o[1 + q];
-    if (rey && o[6] + o[7] + o[8] > 0.0)
+    if ((rey & 1) && o[6] + o[7] + o[8] > 0.0)
         for (int q = 0; q < 6; ++q) f[NF_RE + q] = o[6 + q];
+    if ((rey & 2) && o[4] > 0.0) f[NF_OM] = o[4];
 }
 
 // gradient of a P1 field from its vertex values (Eqs. 39-40), in the element's frame
@@ -1848,14 +1855,16 @@ __global__ void __launch_bounds__(256) k_cfl(const ElemGeo* __restrict__ geo, co
 static inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) / nt); }
 
 template <class R>
-void launch_advance(const AdvanceArgs<R>& a, int64_t n_ub, bool batched, int block, hipStream_t s)
+void launch_advance(const AdvanceArgs<R>& a, int64_t n_ub, bool batched, bool wp_full, int block, hipStream_t s)
 {
     if (n_ub <= 0) return;
     if (block != 64 && block != 128) block = 256;
     if (batched)
         hipLaunchKernelGGL(k_advance_batched<R>, dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
+    else if (wp_full)
+        hipLaunchKernelGGL((k_advance<R, true>), dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
     else
-        hipLaunchKernelGGL(k_advance<R>, dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_advance<R, false>), dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
     hipLaunchKernelGGL(k_wall_resample<R>, dim3(256), dim3(256), 0, s, a.s, (const int32_t*)a.wall_list,
                        (const int32_t*)a.wall_count, a.geo, a.prm, a.meta);
 }
@@ -2006,7 +2015,7 @@ void launch_shift_init(const R* node, int64_t nn, R* shift, hipStream_t s)
 
 // both forms of the state
 #define PDF_INSTANTIATE(R)                                                                               \
-    template void launch_advance<R>(const AdvanceArgs<R>&, int64_t, bool, int, hipStream_t);             \
+    template void launch_advance<R>(const AdvanceArgs<R>&, int64_t, bool, bool, int, hipStream_t);       \
     template hipError_t prepare_element_pass<R>(int);                                                    \
     template size_t element_pass_smem<R>(int);                                                           \
     template void launch_element_pass<R>(const ElementArgs<R>&, const int*, int, hipStream_t);          \

@@ -223,7 +223,7 @@ pdf_status step_once(pdf_ens_s* E, hipStream_t s)
     a.prm = E->d_prm;
     {
         Timed t(E, T_ADVANCE, s);
-        launch_advance<R>(a, E->n_slots_ub, E->n_problems > 1, E->adv_block, s);
+        launch_advance<R>(a, E->n_slots_ub, E->n_problems > 1, E->wp_full, E->adv_block, s);
     }
     HIP_TRY(hipGetLastError());
     pdf_status st = regroup<R>(E, true, true, true, s);
@@ -1248,7 +1248,8 @@ pdf_status pdf_redistribute(pdf_ens E, int32_t problem, int32_t n_min, int64_t* 
 }
 
 pdf_status pdf_elliptic_relaxation(pdf_ens E, const pdf_elliptic_model* consts, double tol, int32_t max_iter,
-                                   double* wp_out, int32_t out_is_device, int32_t* iters_out, void* hip_stream)
+                                   int32_t store, double* wp_out, int32_t out_is_device, int32_t* iters_out,
+                                   void* hip_stream)
 {
     if (iters_out) *iters_out = 0;
     if (!E || E->n_problems != 1 || !(tol > 0.0) || !(tol < 1.0) || max_iter < 0) {
@@ -1267,6 +1268,7 @@ pdf_status pdf_elliptic_relaxation(pdf_ens E, const pdf_elliptic_model* consts, 
     E->stream = s;
     pdf_status st = fem_geometry(E, s);
     if (st == PDF_OK) st = fem_work(E);
+    if (st == PDF_OK && store) st = ensure_own_fields(E, s);
     if (st == PDF_OK) st = fem_check(E, s, "pdf_elliptic_relaxation");
     if (st != PDF_OK) return st;
     FemState& F = E->fem;
@@ -1281,6 +1283,13 @@ pdf_status pdf_elliptic_relaxation(pdf_ens E, const pdf_elliptic_model* consts, 
     fem_set_fixed(F.xfix, F.fixed, g.nn, F.x, s);
     st = fem_cg<9>(E, op, F.b, tol, max_iter, iters_out, s);
     if (st != PDF_OK) return st;
+    if (store) {
+        if (!E->wp_full) drop_graphs(E);   // captured steps run the six-component particle loop
+        E->wp_full = true;
+        fem_store_wp(F.x, g.nn, E->dg.node, s);
+        if (g.node32) launch_f64_to_f32(g.node, g.node32, g.nn * NODE_STRIDE, s);
+        HIP_TRY(hipGetLastError());
+    }
     if (wp_out) {
         const size_t bytes = sizeof(double) * 9 * g.nn;
         HIP_TRY(hipMemcpyAsync(wp_out, F.x, bytes, out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
@@ -1342,6 +1351,8 @@ pdf_status pdf_pressure_projection(pdf_ens E, double dt, double cp, double tol, 
     else
         fem_correct_particles<double>(cur(E).as<double>(), E->d_meta, E->n_slots_ub, F.gdP, scale, s);
     if (g.node32) launch_f64_to_f32(g.node, g.node32, nn * NODE_STRIDE, s);
+    // with statistics feedback on, the corrected mean velocity is the one fed back
+    if (E->fb_on) apply_feedback(E, s);
     HIP_TRY(hipGetLastError());
     if (dp_out)
         HIP_TRY(hipMemcpyAsync(dp_out, F.x, sizeof(double) * nn,
@@ -1599,7 +1610,7 @@ pdf_status pdf_set_feedback(pdf_ens E, int32_t enable, double alpha, int32_t fee
     E->stream = s;
     E->fb_on = enable != 0;
     E->fb_alpha = alpha;
-    E->fb_rey = feed_rey != 0;
+    E->fb_rey = feed_rey & 3;
     if (!enable) return PDF_OK;
     DevGrid& g = E->dg;
     {

@@ -10,10 +10,11 @@
 
 namespace pdfgpu {
 
-// Per-node field record, 22 doubles (176 B, 16-B aligned):
-// grad<P>(2), wp(6), <U>(3), lap<U>(3), <omega>(1), R(6), pad(1)
-constexpr int NODE_STRIDE = 22;
-enum { NF_GP = 0, NF_WP = 2, NF_MU = 8, NF_LAP = 11, NF_OM = 14, NF_RE = 15 };
+// Per-node field record, 24 doubles (192 B, 16-B aligned):
+// grad<P>(2), wp_11, wp_22, wp_33, wp_12, wp_13, wp_23 (6), <U>(3), lap<U>(3), <omega>(1),
+// R(6), wp_21, wp_31, wp_32 (3; the elliptic-relaxation tensor is not symmetric, Eq. 13)
+constexpr int NODE_STRIDE = 24;
+enum { NF_GP = 0, NF_WP = 2, NF_MU = 8, NF_LAP = 11, NF_OM = 14, NF_RE = 15, NF_WPT = 21 };
 
 // Edge kinds after classification.
 enum : uint8_t { KIND_INTERIOR = 0, KIND_WALL = 1, KIND_SLIP = 2, KIND_PERIODIC = 3 };
@@ -211,6 +212,7 @@ struct pdf_ens_s {
     std::vector<int> tiers;         // particles per lane of the wavefront tiers, ascending
     bool ctl_valid = false;     // the current buffer holds the canonical order of a pass
     bool any_proj = false;      // some problem conditions by Fox's projection
+    bool wp_full = false;       // the nodal wp field has nine components (stored by the solve)
     FemState fem;
     int32_t* redist_plan = nullptr;  // [redist_cap][4] moves of the last redistribution
     int64_t redist_cap = 0;

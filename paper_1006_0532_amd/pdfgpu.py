@@ -104,7 +104,7 @@ def load(path: str = LIB_PATH):
         "pdf_set_feedback": [vp, C.c_int32, C.c_double, C.c_int32, vp],
         "pdf_cfl_dt": [vp, C.c_int32, C.c_double, dp, vp],
         "pdf_redistribute": [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64), vp],
-        "pdf_elliptic_relaxation": [vp, C.POINTER(EllipticModel), C.c_double, C.c_int32, vp, C.c_int32,
+        "pdf_elliptic_relaxation": [vp, C.POINTER(EllipticModel), C.c_double, C.c_int32, C.c_int32, vp, C.c_int32,
                                     C.POINTER(C.c_int32), vp],
         "pdf_pressure_projection": [vp, C.c_double, C.c_double, C.c_double, C.c_int32, vp, C.c_int32,
                                     C.POINTER(C.c_int32), vp],
@@ -280,10 +280,11 @@ class Ensemble:
         _check(load().pdf_timing(self.h, int(enable), ms, cnt))
         return {TIMER_NAMES[i]: (ms[i], cnt[i]) for i in range(PDF_NTIMERS)}
 
-    def set_feedback(self, enable: bool = True, alpha: float = 1.0, feed_rey: bool = False):
+    def set_feedback(self, enable: bool = True, alpha: float = 1.0, feed_rey: bool = False,
+                     feed_omega: bool = False):
         """Feed the nodal statistics back into the fields now and after every step."""
-        _check(load().pdf_set_feedback(self.h, int(bool(enable)), float(alpha), int(bool(feed_rey)),
-                                       C.c_void_p(self.stream)))
+        flags = int(bool(feed_rey)) | (2 if feed_omega else 0)
+        _check(load().pdf_set_feedback(self.h, int(bool(enable)), float(alpha), flags, C.c_void_p(self.stream)))
 
     def cfl_dt(self, cfl: float = 0.7, problem: int = 0) -> float:
         """Time step of Eq. (26) from the last statistics."""
@@ -297,14 +298,16 @@ class Ensemble:
         _check(load().pdf_redistribute(self.h, int(problem), int(n_min), C.byref(v), C.c_void_p(self.stream)))
         return int(v.value)
 
-    def elliptic_relaxation(self, consts: dict | None = None, tol: float = 1e-12, max_iter: int = 20000):
-        """Eq. (12) from the current statistics: (wp [nn, 3, 3], CG iterations)."""
+    def elliptic_relaxation(self, consts: dict | None = None, tol: float = 1e-12, max_iter: int = 20000,
+                            store: bool = False):
+        """Eq. (12) from the current statistics: (wp [nn, 3, 3], CG iterations); store makes
+        the solution the ensemble's wp field for the following steps."""
         nn = self.grids[0].nn
         out = np.empty((nn, 3, 3))
         it = C.c_int32()
         m = None if consts is None else C.byref(EllipticModel(**consts))
-        _check(load().pdf_elliptic_relaxation(self.h, m, float(tol), int(max_iter), out.ctypes.data_as(C.c_void_p), 0,
-                                              C.byref(it), C.c_void_p(self.stream)))
+        _check(load().pdf_elliptic_relaxation(self.h, m, float(tol), int(max_iter), int(bool(store)),
+                                              out.ctypes.data_as(C.c_void_p), 0, C.byref(it), C.c_void_p(self.stream)))
         return out, int(it.value)
 
     def pressure_projection(self, dt: float, cp: float = 1e-3, tol: float = 1e-12, max_iter: int = 50000):

@@ -57,6 +57,6 @@ def test_option_and_tuning_argument_errors():
     assert L.pdf_redistribute(None, -1, 3, ctypes.byref(moves), None) == -1
     assert moves.value == 0
     it = ctypes.c_int32(5)
-    assert L.pdf_elliptic_relaxation(None, None, 1e-10, 100, None, 0, ctypes.byref(it), None) == -1
+    assert L.pdf_elliptic_relaxation(None, None, 1e-10, 100, 0, None, 0, ctypes.byref(it), None) == -1
     assert it.value == 0
     assert L.pdf_pressure_projection(None, 1e-3, 1e-3, 1e-10, 100, None, 0, None, None) == -1

@@ -84,3 +84,33 @@ def test_pressure_projection_parity(gpu, case):
         rep, excl = compare_states(ge.export(), oe.export(), frame, length, excl)
         compare_stats(ge.stats(), oe.stats())
     assert len(excl) <= 2
+
+
+def test_closed_loop_parity(gpu):
+    """Table 1 order on the channel: every step first solves Eq. (12) from the statistics of
+    the step before and makes all nine wp_ij the particles' field, then advances the
+    particles, projects the pressure (Eqs. 30-33) with the correction of Eq. (31), and feeds
+    the corrected <U>, the Reynolds stresses and <omega> back."""
+    name, mesh, f, ini = _cases()[0]
+    _say("test_closed_loop_parity")
+    mo = W.model_constants()
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    ex = og.export()
+    frame, area = ex["frame"], ex["area"]
+    proj = fem.Projection(mesh, og, f.grad_p)
+    ge.set_feedback(True, 1.0, feed_rey=True, feed_omega=True)
+    oe.feedback(1.0, True, True)
+    excl = set()
+    for n in range(3):
+        wpg, _ = ge.elliptic_relaxation(tol=1e-13, store=True)
+        wpo = fem.elliptic_relaxation(mesh, frame, area, oe.stats(), mo)
+        og.set_wp(wpo)
+        assert np.abs(wpg - wpo).max() <= 1e-8 * np.abs(wpo).max(), n
+        oe.step(1e-3)
+        ge.step(1e-3)
+        proj.apply(oe, 1e-3, cp=1e-3, rho=mo["rho"])
+        ge.pressure_projection(1e-3, cp=1e-3, tol=1e-13)
+        oe.feedback(1.0, True, True)
+        rep, excl = compare_states(ge.export(), oe.export(), frame, mesh.period_x, excl)
+        compare_stats(ge.stats(), oe.stats())
+    assert len(excl) <= 2
