@@ -70,6 +70,24 @@ void fem_mass_rhs(const FemOp& op, const double* f, double* b, hipStream_t s);
 // x = Dirichlet value where fixed, else keep x (nine components)
 void fem_set_fixed(const double* xfix, const uint16_t* fixed, int64_t nn, double* x, hipStream_t s);
 
+// Assembled stiffness matrix (CSR, one row per node, columns ascending) for the scalar
+// pressure system, whose coefficients do not change: y = K p and the block partials of
+// p . y in one pass
+void fem_csr_apply_dot(const int32_t* row_ptr, const int32_t* col, const double* val, const double* x, int64_t nn,
+                       double* y, double* partial, int nblocks, hipStream_t s);
+int fem_csr_blocks(int64_t nn);
+// CG steps of one component with fused reductions (partial sums per block, then one block):
+// alpha = rz / pAp from the partials of p.Ap; x += alpha p, r -= alpha Ap, z = r / diag with
+// the partials of r.z and r.r; beta = rz_new / rz (rz <- rz_new, rr stored); p = z + beta p.
+// Scalars sc = [rz][pAp][rz_new][rr][alpha][beta].
+void fem_cg1_alpha(const double* partial, int nblocks, double* sc, hipStream_t s);
+void fem_cg1_xr_dot(const double* sc, const double* p, const double* Ap, const double* diag, int64_t nn, double* x,
+                    double* r, double* z, double* partial, int nblocks, hipStream_t s);
+void fem_cg1_beta(const double* partial, int nblocks, double* sc, hipStream_t s);
+// diag of the CSR matrix
+void fem_csr_diag(const int32_t* row_ptr, const int32_t* col, const double* val, int64_t nn, double* d,
+                  hipStream_t s);
+
 // nodal wp records (nine components) from the solution [nn][9] (row-major ij)
 void fem_store_wp(const double* wp9, int64_t nn, double* node, hipStream_t s);
 

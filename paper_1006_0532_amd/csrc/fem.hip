@@ -461,7 +461,131 @@ __global__ void __launch_bounds__(256) k_fem_store_wp(const double* __restrict__
     f[NF_WPT + 2] = w[7];
 }
 
+
+// ---- assembled scalar operator (pressure) with fused reductions ----
+__device__ __forceinline__ void block_partial(double v, double* red, double* out)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v = wave_sum_double(v);
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void __launch_bounds__(256) k_csr_apply_dot(const int32_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ val, const double* __restrict__ x,
+                                                       int64_t nn, double* __restrict__ y, double* __restrict__ partial)
+{
+    __shared__ double red[4];
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double pq = 0.0;
+    if (n < nn) {
+        double acc = 0.0;
+        for (int32_t j = row_ptr[n]; j < row_ptr[n + 1]; ++j) acc += val[j] * x[col[j]];
+        y[n] = acc;
+        pq = x[n] * acc;
+    }
+    block_partial(pq, red, partial + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_csr_diag(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                                  const double* __restrict__ val, int64_t nn, double* __restrict__ d)
+{
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= nn) return;
+    double v = 1.0;
+    for (int32_t j = row_ptr[n]; j < row_ptr[n + 1]; ++j)
+        if (col[j] == n) v = val[j];
+    d[n] = v;
+}
+
+// sum of nb partials (stride q apart, nq per block) by one workgroup in a fixed order
+__device__ __forceinline__ double finish_sum(const double* partial, int nb, int nq, int q, double* red)
+{
+    double t = 0.0;
+    for (int k = threadIdx.x; k < nb; k += 256) t += partial[(int64_t)k * nq + q];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    t = wave_sum_double(t);
+    if (lane == 0) red[w] = t;
+    __syncthreads();
+    const double v = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_cg1_alpha(const double* __restrict__ partial, int nb, double* __restrict__ sc)
+{
+    __shared__ double red[4];
+    const double pap = finish_sum(partial, nb, 1, 0, red);
+    if (threadIdx.x == 0) {
+        sc[1] = pap;
+        sc[4] = pap > 0.0 ? sc[0] / pap : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_cg1_xr_dot(const double* __restrict__ sc, const double* __restrict__ p,
+                                                    const double* __restrict__ Ap, const double* __restrict__ diag,
+                                                    int64_t nn, double* __restrict__ x, double* __restrict__ r,
+                                                    double* __restrict__ z, double* __restrict__ partial)
+{
+    __shared__ double red[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (i < nn) {
+        const double al = sc[4];
+        x[i] += al * p[i];
+        const double ri = r[i] - al * Ap[i];
+        const double zi = ri / diag[i];
+        r[i] = ri;
+        z[i] = zi;
+        rz = ri * zi;
+        rr = ri * ri;
+    }
+    block_partial(rz, red, partial + 2 * blockIdx.x);
+    __syncthreads();
+    block_partial(rr, red, partial + 2 * blockIdx.x + 1);
+}
+
+__global__ void __launch_bounds__(256) k_cg1_beta(const double* __restrict__ partial, int nb, double* __restrict__ sc)
+{
+    __shared__ double red[4];
+    const double rzn = finish_sum(partial, nb, 2, 0, red);
+    const double rr = finish_sum(partial, nb, 2, 1, red);
+    if (threadIdx.x == 0) {
+        const double rz = sc[0];
+        sc[5] = rz > 0.0 ? rzn / rz : 0.0;
+        sc[0] = rzn;
+        sc[2] = rzn;
+        sc[3] = rr;
+    }
+}
+
 }  // namespace
+
+int fem_csr_blocks(int64_t nn) { return (int)blocks(nn > 0 ? nn : 1, 256); }
+void fem_csr_apply_dot(const int32_t* row_ptr, const int32_t* col, const double* val, const double* x, int64_t nn,
+                       double* y, double* partial, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_csr_apply_dot, dim3(nblocks), dim3(256), 0, s, row_ptr, col, val, x, nn, y, partial);
+}
+void fem_csr_diag(const int32_t* row_ptr, const int32_t* col, const double* val, int64_t nn, double* d, hipStream_t s)
+{
+    if (nn > 0) hipLaunchKernelGGL(k_csr_diag, dim3(blocks(nn, 256)), dim3(256), 0, s, row_ptr, col, val, nn, d);
+}
+void fem_cg1_alpha(const double* partial, int nblocks, double* sc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg1_alpha, dim3(1), dim3(256), 0, s, partial, nblocks, sc);
+}
+void fem_cg1_xr_dot(const double* sc, const double* p, const double* Ap, const double* diag, int64_t nn, double* x,
+                    double* r, double* z, double* partial, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg1_xr_dot, dim3(nblocks), dim3(256), 0, s, sc, p, Ap, diag, nn, x, r, z, partial);
+}
+void fem_cg1_beta(const double* partial, int nblocks, double* sc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg1_beta, dim3(1), dim3(256), 0, s, partial, nblocks, sc);
+}
 
 void fem_store_wp(const double* wp9, int64_t nn, double* node, hipStream_t s)
 {

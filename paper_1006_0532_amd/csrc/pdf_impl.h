@@ -143,6 +143,9 @@ struct FemState {
     double* sc = nullptr;         // CG scalars [6][9]
     double* partial = nullptr;    // reduction partials
     bool pressure = false;        // P and gp0 set up
+    int32_t *csr_rp = nullptr, *csr_col = nullptr;   // assembled stiffness matrix of the grid
+    double* csr_val = nullptr;
+    double* partial2 = nullptr;   // block partials of the assembled-matrix CG
     double *P = nullptr, *gp0 = nullptr, *gP = nullptr, *gdP = nullptr;       // [nn], [nn][2], [ne][2]
 };
 
