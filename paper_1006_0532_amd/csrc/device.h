@@ -135,9 +135,18 @@ __host__ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, doub
 // uniform on (0, 1) from the top 24 bits: ((w >> 8) + 1/2) * 2^-24, exact in float
 __device__ __forceinline__ float u01f(uint32_t w) { return ((float)(w >> 8) + 0.5f) * 5.9604644775390625e-8f; }
 
+// uniform on (0, 1) from all 32 bits with the relative precision of a float at every
+// magnitude: (w + 1/2) 2^-32, w rounded to 24 significant bits, kept below 1.  The radius
+// of the Box-Muller map takes its logarithm, so small u (the tail of the Gaussian) must not
+// lose the low bits that the 24-bit map above drops.
+__device__ __forceinline__ float u01f_fine(uint32_t w)
+{
+    return fminf(fmaf((float)w, 0x1p-32f, 0x1p-33f), 0x1.fffffep-1f);
+}
+
 __device__ __forceinline__ void box_muller_f(uint32_t a, uint32_t b, float& z0, float& z1)
 {
-    const float r = sqrtf(-2.0f * logf(u01f(a)));
+    const float r = sqrtf(-2.0f * logf(u01f_fine(a)));
     float s, c;
     sincospif(2.0f * u01f(b), &s, &c);   // sin, cos of 2 pi u; 2u is exact
     z0 = r * c;
