@@ -5,9 +5,10 @@ element (8e7 particles), dt = 2e-4; one timed step = pdf_step (advance, track, g
 bin, mix, statistics) + pdf_control(150, 250) (number control), inputs resident in HBM.
 Prints one JSON line with whole-job throughput, the roofline of the dominant kernel
 (timed with HIP events on the ensemble's stream), the CPU oracle timed on a bounded
-sample of the same workload, and the two other forms: the same workload in mixed
-precision, and 64 uneven independent problems advanced as one batched ensemble against
-the same problems advanced one at a time.
+sample of the same workload, and the other forms: the same workload in mixed precision,
+64 uneven independent problems advanced as one batched ensemble against the same problems
+advanced one at a time, and the large street canyon (4e6 triangles, about 4.8e8
+particles) in mixed precision with per-kernel HBM rates.
 """
 from __future__ import annotations
 
@@ -77,6 +78,8 @@ def parse():
     p.add_argument("--no-forms", action="store_true",
                    help="skip the mixed-precision and batched measurements")
     p.add_argument("--form-steps", type=int, default=10)
+    p.add_argument("--large-mixed-only", action="store_true",
+                   help="run only the large street canyon in the mixed form and print its figures")
     p.add_argument("--no-eulerian", action="store_true",
                    help="skip timing the elliptic-relaxation and pressure-projection solves")
     p.add_argument("--batched-problems", type=int, default=64)
@@ -172,6 +175,51 @@ def mixed_form(args, mesh, f, mo, ini, dt, ctl):
     return out
 
 
+# algorithmic bytes per particle of the mixed form (U, omega, psi, w in FP32)
+MIXED_BYTES_PER_PARTICLE = {
+    # read x, y (16), U, omega (16), pid 8, elem 4; write x, y, U, omega, elem, arrival rank
+    "advance": 16 + 16 + 8 + 4 + 16 + 16 + 4 + 4,
+    # read idx 4, U 12, pid 8, x, y 16, omega, psi, w 12; write the state (52)
+    "element_pass": 4 + 12 + 8 + 16 + 12 + 52,
+    "scatter": 4 + 4 + 4,
+}
+
+
+def large_mixed_form(args):
+    """The large street canyon (4e6 triangles, 120 particles per element, about 4.8e8
+    particles) in the mixed form with number control [90, 150]: throughput and per-kernel
+    algorithmic HBM rates."""
+    from paper_1006_0532_amd import pdfgpu, workloads as W
+    mesh, f, mo, ini = W.cavity_huge()
+    wl = W.WORKLOADS["cavity_huge"]
+    dt, ctl = wl["dt"], wl["control"]
+    n0 = mesh.n_elems * ini["ppe"]
+    grid = pdfgpu.Grid(mesh, f, mo)
+    ens = pdfgpu.Ensemble(grid, ini, capacity=int(1.3 * n0) + 1024, precision=pdfgpu.PDF_MIXED)
+    for _ in range(2):
+        ens.step(dt)
+        ens.control(*ctl)
+    ens.timing(True)
+    live, el = timed_steps(ens, dt, args.form_steps, ctl)
+    tim = ens.timing(False)
+    mean_live = live / args.form_steps
+    per = {}
+    for k, v in tim.items():
+        if v[1] == 0:
+            continue
+        avg = v[0] / v[1]
+        per[k] = {"ms": round(avg, 4)}
+        if k in MIXED_BYTES_PER_PARTICLE:
+            gbs = MIXED_BYTES_PER_PARTICLE[k] * mean_live / (avg * 1e-3) / 1e9
+            per[k].update({"GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+    out = {"workload": "cavity_huge", "triangles": mesh.n_elems, "particles": n0, "ppe": ini["ppe"],
+           "bins": list(ini["bins"]), "control": list(ctl), "dt": dt, "steps": args.form_steps,
+           "value": live / el, "ms_per_step": 1e3 * el / args.form_steps, "per_kernel": per}
+    ens.close()
+    grid.close()
+    return out
+
+
 def mixed_error(mesh, f, mo, ini, dt, steps):
     """Nodal statistics of the mixed form against the FP64 form on the full workload after
     `steps` steps without number control (control decisions on counts that differ by one
@@ -240,6 +288,9 @@ def main():
     from paper_1006_0532_amd import pdfgpu, workloads as W
 
     torch.cuda.set_device(0)
+    if args.large_mixed_only:
+        print(json.dumps(large_mixed_form(args)), flush=True)
+        return
     if args.copy_calib:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
@@ -348,6 +399,8 @@ def main():
         b = forms["batched"]
         b["speedup_vs_plain"] = b["fp64"]["value"] / b["plain_fp64_one_at_a_time"]["value"]
         print(f"[bench] batched: {json.dumps(b)}", file=sys.stderr, flush=True)
+        forms["cavity_huge_mixed"] = large_mixed_form(args)
+        print(f"[bench] cavity_huge mixed: {json.dumps(forms['cavity_huge_mixed'])}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
