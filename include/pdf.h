@@ -336,7 +336,7 @@ pdf_status pdf_cfl_dt(pdf_ens ens, int32_t problem, double cfl, double* dt_out, 
  *  use_graph  1: pdf_step replays every two steps from a captured HIP graph on a
  *             stream of the ensemble (ordered after and before hip_stream by events),
  *             captured again when the slot bound or a time step changes;
- *  adv_block  workgroup size of the particle loop: 64, 128 or 256;
+ *  adv_block  workgroup size of the particle loop: 64 (the default), 128 or 256;
  *  ppl        particles per lane of the wavefront element kernel (elements with more
  *             than 64 x ppl particles take the workgroup kernel): 1..6 or 8. */
 typedef struct {

@@ -1007,14 +1007,39 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// wavefronts per workgroup of the wavefront element kernel (LDS stays within 64 KiB), and
-// the wavefronts per SIMD the register budget is set for (up to five particles per lane
-// fit 128 registers: four wavefronts per SIMD, as the LDS of four workgroups per CU allows)
+// wavefronts per workgroup of the wavefront element kernel (two: small workgroups fill the
+// CUs more evenly than four, and LDS stays within 64 KiB), and the wavefronts per SIMD the
+// register budget is set for (up to five particles per lane fit 128 registers: four
+// wavefronts per SIMD)
 template <int PPL>
 struct WaveBlock {
-    static constexpr int waves = PPL >= 6 ? 2 : 4;
+    static constexpr int waves = 2;
     static constexpr int per_simd = PPL <= 5 ? 4 : 1;
 };
+
+// Full rank of the first sort level: each lane counts, for its particles in rows r < K, the
+// 31-bit keys below its own over the whole element (n8 keys, padded).  Rows whose particles
+// all lie beyond n (K = the rows in use, a wavefront-uniform count) are skipped.
+template <int PPL, int K = PPL>
+__device__ __forceinline__ void rank_full(const uint32_t* __restrict__ k32, int n8, const uint32_t (&m32)[PPL],
+                                          int (&rk)[PPL], int rows)
+{
+    if constexpr (K > 1) {
+        if (rows < K) {
+            rank_full<PPL, K - 1>(k32, n8, m32, rk, rows);
+            return;
+        }
+    }
+    auto lt = [](uint32_t a, uint32_t b) { return (int)((a - b) >> 31); };
+    for (int q = 0; q < n8; q += 8) {
+        const uint4 ka = *reinterpret_cast<const uint4*>(k32 + q);
+        const uint4 kb = *reinterpret_cast<const uint4*>(k32 + q + 4);
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+            rk[r] += lt(ka.x, m32[r]) + lt(ka.y, m32[r]) + lt(ka.z, m32[r]) + lt(ka.w, m32[r]) + lt(kb.x, m32[r]) +
+                     lt(kb.y, m32[r]) + lt(kb.z, m32[r]) + lt(kb.w, m32[r]);
+    }
+}
 
 // One wavefront per element (up to 64*PPL particles, PPL per lane).  Lanes own particles
 // in load order while the three sort levels rank (U_l, pid) keys staged in LDS; then each
@@ -1194,14 +1219,7 @@ k_element_wave(ElementArgs<R> a, int n_below, int last)
 #pragma unroll
         for (int r = 0; r < PPL; ++r) rk[r] = 0;
         if (l == 0) {
-            for (int q = 0; q < n8; q += 8) {
-                const uint4 ka = *reinterpret_cast<const uint4*>(k32 + q);
-                const uint4 kb = *reinterpret_cast<const uint4*>(k32 + q + 4);
-#pragma unroll
-                for (int r = 0; r < PPL; ++r)
-                    rk[r] += lt(ka.x, m32[r]) + lt(ka.y, m32[r]) + lt(ka.z, m32[r]) + lt(ka.w, m32[r]) +
-                             lt(kb.x, m32[r]) + lt(kb.y, m32[r]) + lt(kb.z, m32[r]) + lt(kb.w, m32[r]);
-            }
+            rank_full<PPL>(k32, n8, m32, rk, (n + 63) >> 6);
         } else {
 #pragma unroll
             for (int r = 0; r < PPL; ++r)

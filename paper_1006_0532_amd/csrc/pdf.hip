@@ -1191,14 +1191,16 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
     }
     // element pass: a wavefront per element holds up to 64 * ppl particles (ppl from the
     // largest set-up count with 30 % headroom); larger elements go to the workgroup
-    // kernel, whose on-chip path takes up to lds_max particles within 64 KiB of LDS
+    // kernel, whose on-chip path takes up to lds_max particles within 64 KiB of LDS.  The
+    // smallest tier holds the smallest set-up count without headroom: the elements that
+    // stay at or below it take fewer registers and rank fewer rows.
     int64_t ppe_max = 1, ppe_min = INT32_MAX;
     for (auto& d : E->descs) {
         ppe_max = std::max<int64_t>(ppe_max, d.ppe);
         if (d.ppe > 0) ppe_min = std::min<int64_t>(ppe_min, d.ppe);
     }
     E->ppl = ppl_for(ppe_max);
-    E->ppl_min = ppl_for(ppe_min == INT32_MAX ? ppe_max : ppe_min);
+    E->ppl_min = (int)std::max<int64_t>(1, ((ppe_min == INT32_MAX ? ppe_max : ppe_min) + 63) / 64);
     set_tiers(E);
     HIP_TRY(hipMemcpyAsync(E->d_prm, E->h_prm.data(), sizeof(ProbParams) * n_problems, hipMemcpyHostToDevice, s));
     st = E->precision == PDF_MIXED ? setup_precision<float>(E, s) : setup_precision<double>(E, s);
@@ -1789,7 +1791,7 @@ pdf_status pdf_autotune(pdf_ens E, const double* dt, int32_t steps_per_trial, vo
     std::vector<pdf_options> cand;
     const int p0 = base.ppl;
     const int ppls[3] = {p0 > 1 ? (p0 == 8 ? 6 : p0 - 1) : 1, p0, p0 >= 6 ? 8 : p0 + 1};
-    for (int b : {128, 256})
+    for (int b : {64, 128, 256})
         for (int q = 0; q < 3; ++q) {
             if (q > 0 && ppls[q] == ppls[q - 1]) continue;
             cand.push_back(pdf_options{base.use_graph, b, ppls[q]});

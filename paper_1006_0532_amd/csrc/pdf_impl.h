@@ -194,7 +194,7 @@ struct pdf_ens_s {
     int64_t t_n[pdfgpu::T_N] = {0};
     int lds_max = 0;            // particles per element on chip in the workgroup kernel
     int ppl = 4;                // particles per lane in the wavefront kernel
-    int adv_block = 256;        // threads per workgroup of the particle loop
+    int adv_block = 64;         // threads per workgroup of the particle loop
     // statistics feedback after every step
     bool fb_on = false;
     double fb_alpha = 1.0;
