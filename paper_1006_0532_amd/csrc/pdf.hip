@@ -1191,16 +1191,15 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
     }
     // element pass: a wavefront per element holds up to 64 * ppl particles (ppl from the
     // largest set-up count with 30 % headroom); larger elements go to the workgroup
-    // kernel, whose on-chip path takes up to lds_max particles within 64 KiB of LDS.  The
-    // smallest tier holds the smallest set-up count without headroom: the elements that
-    // stay at or below it take fewer registers and rank fewer rows.
+    // kernel, whose on-chip path takes up to lds_max particles within 64 KiB of LDS.
+    // Number control later sets the first tier to its upper bound.
     int64_t ppe_max = 1, ppe_min = INT32_MAX;
     for (auto& d : E->descs) {
         ppe_max = std::max<int64_t>(ppe_max, d.ppe);
         if (d.ppe > 0) ppe_min = std::min<int64_t>(ppe_min, d.ppe);
     }
     E->ppl = ppl_for(ppe_max);
-    E->ppl_min = (int)std::max<int64_t>(1, ((ppe_min == INT32_MAX ? ppe_max : ppe_min) + 63) / 64);
+    E->ppl_min = ppl_for(ppe_min == INT32_MAX ? ppe_max : ppe_min);
     set_tiers(E);
     HIP_TRY(hipMemcpyAsync(E->d_prm, E->h_prm.data(), sizeof(ProbParams) * n_problems, hipMemcpyHostToDevice, s));
     st = E->precision == PDF_MIXED ? setup_precision<float>(E, s) : setup_precision<double>(E, s);
@@ -1465,6 +1464,16 @@ pdf_status pdf_control(pdf_ens E, int32_t n_min, int32_t n_max, pdf_control_repo
     if (!E->ctl_valid) {
         set_error("pdf_control: no element pass since the last control");
         return PDF_E_STATE;
+    }
+    // the first wavefront tier of the element pass holds the upper bound: after control
+    // nearly every element is at or below it, and the few that the next particle loop
+    // pushes above take the next tier (fewer particles per lane: fewer live registers and
+    // rows to rank; a tier that most elements fall past would cost a second sweep)
+    const int hint = std::min(E->ppl, n_max > 64 * 6 ? 8 : (n_max + 63) / 64);
+    if (hint != E->ppl_min) {
+        E->ppl_min = hint;
+        set_tiers(E);
+        drop_graphs(E);   // captured steps launch the old tiers
     }
     return E->precision == PDF_MIXED ? control_impl<float>(E, n_min, n_max, report, s)
                                      : control_impl<double>(E, n_min, n_max, report, s);
