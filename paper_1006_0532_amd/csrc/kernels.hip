@@ -621,7 +621,10 @@ __device__ __forceinline__ bool key_less(const SortKey& a, uint64_t bk, uint64_t
     return a.k < bk || (a.k == bk && a.p < bp);
 }
 
-// groups per level of the sort-and-divide procedure (see the oracle's reading)
+// groups per level of the sort-and-divide procedure (App. A; Sec. 3.5 asks for at least m
+// particles per bin): level l splits each group into min(b_l, max(1, floor(n / (m P))))
+// groups, P the product of the earlier levels' counts, and once a level gets fewer groups
+// than requested the later levels take one; returns the number of bins
 __device__ __forceinline__ int bin_structure(int n, int b0, int b1, int b2, int m, int& g0, int& g1, int& g2)
 {
     const int bl[3] = {b0, b1, b2};
@@ -1017,30 +1020,6 @@ struct WaveBlock {
     static constexpr int per_simd = PPL <= 5 ? 4 : 1;
 };
 
-// Full rank of the first sort level: each lane counts, for its particles in rows r < K, the
-// 31-bit keys below its own over the whole element (n8 keys, padded).  Rows whose particles
-// all lie beyond n (K = the rows in use, a wavefront-uniform count) are skipped.
-template <int PPL, int K = PPL>
-__device__ __forceinline__ void rank_full(const uint32_t* __restrict__ k32, int n8, const uint32_t (&m32)[PPL],
-                                          int (&rk)[PPL], int rows)
-{
-    if constexpr (K > 1) {
-        if (rows < K) {
-            rank_full<PPL, K - 1>(k32, n8, m32, rk, rows);
-            return;
-        }
-    }
-    auto lt = [](uint32_t a, uint32_t b) { return (int)((a - b) >> 31); };
-    for (int q = 0; q < n8; q += 8) {
-        const uint4 ka = *reinterpret_cast<const uint4*>(k32 + q);
-        const uint4 kb = *reinterpret_cast<const uint4*>(k32 + q + 4);
-#pragma unroll
-        for (int r = 0; r < K; ++r)
-            rk[r] += lt(ka.x, m32[r]) + lt(ka.y, m32[r]) + lt(ka.z, m32[r]) + lt(ka.w, m32[r]) + lt(kb.x, m32[r]) +
-                     lt(kb.y, m32[r]) + lt(kb.z, m32[r]) + lt(kb.w, m32[r]);
-    }
-}
-
 // One wavefront per element (up to 64*PPL particles, PPL per lane).  Lanes own particles
 // in load order while the three sort levels rank (U_l, pid) keys staged in LDS; then each
 // lane takes the particles at canonical positions lane + 64 r, so bin sums, partial sums
@@ -1170,15 +1149,87 @@ k_element_wave(ElementArgs<R> a, int n_below, int last)
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         if (proj && l > 0) break;
+        if (l == 0) {
+            // first level, the whole element one group: exact ranks by a counting pass over
+            // 64 buckets of equal width in the key's value (a monotone map: a lower bucket
+            // holds only smaller keys), then (key, pid) comparisons inside the particle's
+            // own bucket.  Keys in bucket order use kk / kpid; counts and starts use the
+            // 31-bit key slice.
+            int* hist = reinterpret_cast<int*>(k32);
+            int* bst = hist + 64;
+            double v[PPL];
+            uint64_t mk[PPL];
+            double vlo = __builtin_inf(), vhi = -__builtin_inf();
+#pragma unroll
+            for (int r = 0; r < PPL; ++r) {
+                if constexpr (PROJ)
+                    v[r] = proj ? fk[r] : (double)U0[r];
+                else
+                    v[r] = (double)U0[r];
+                mk[r] = order_bits(v[r]);
+                if (lane + 64 * r < n) {
+                    vlo = fmin(vlo, v[r]);
+                    vhi = fmax(vhi, v[r]);
+                }
+            }
+            vlo = -wave_max_double(-vlo);
+            vhi = wave_max_double(vhi);
+            const double span = vhi - vlo;
+            const double scale = span > 0.0 ? 64.0 / span : 0.0;
+            hist[lane] = 0;
+            wave_sync();
+            int bk[PPL], off[PPL];
+#pragma unroll
+            for (int r = 0; r < PPL; ++r) {
+                bk[r] = off[r] = 0;
+                if (lane + 64 * r < n) {
+                    // a product that is not a number (0 x inf when the span underflows)
+                    // goes to bucket 0, like the smallest key
+                    const double t = (v[r] - vlo) * scale;
+                    bk[r] = t >= 63.0 ? 63 : (t > 0.0 ? (int)t : 0);
+                    off[r] = atomicAdd(&hist[bk[r]], 1);
+                }
+            }
+            wave_sync();
+            const int cnt = hist[lane];
+            int inc = cnt;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int t = __shfl_up(inc, o);
+                if (lane >= o) inc += t;
+            }
+            bst[lane] = inc - cnt;
+            wave_sync();
+#pragma unroll
+            for (int r = 0; r < PPL; ++r)
+                if (lane + 64 * r < n) {
+                    const int q = bst[bk[r]] + off[r];
+                    kk[q] = mk[r];
+                    kpid[q] = pd[r];
+                }
+            wave_sync();
+#pragma unroll
+            for (int r = 0; r < PPL; ++r)
+                if (lane + 64 * r < n) {
+                    const int q0 = bst[bk[r]], q1 = q0 + hist[bk[r]];
+                    int rank = q0;
+                    for (int q = q0; q < q1; ++q) {
+                        const uint64_t kq = kk[q];
+                        rank += (kq < mk[r] || (kq == mk[r] && kpid[q] < pd[r])) ? 1 : 0;
+                    }
+                    pos[r] = rank;
+                }
+            wave_sync();
+            C *= gl[0];
+            continue;
+        }
+        // later levels: rank inside the groups the previous level formed
         uint64_t mk[PPL];
         int lo[PPL], hi[PPL];
         uint64_t kmin = ~0ull, kmax = 0ull;
 #pragma unroll
         for (int r = 0; r < PPL; ++r) {
-            if constexpr (PROJ)
-                mk[r] = proj ? order_bits(fk[r]) : order_bits(l == 0 ? U0[r] : (l == 1 ? U1[r] : U2[r]));
-            else
-                mk[r] = order_bits(l == 0 ? U0[r] : (l == 1 ? U1[r] : U2[r]));
+            mk[r] = order_bits(l == 1 ? U1[r] : U2[r]);
             const int t = div_small((int)C * pos[r], n);
             lo[r] = div_small(t * n + (int)C - 1, (int)C);
             hi[r] = div_small((t + 1) * n + (int)C - 1, (int)C);
@@ -1208,9 +1259,6 @@ k_element_wave(ElementArgs<R> a, int n_below, int last)
                 k32[pos[r]] = m32[r];
             }
         }
-        // pad to a multiple of 8 with the largest 31-bit key (never below a real key)
-        const int n8 = (n + 7) & ~7;
-        for (int q = n + lane; q < n8; q += 64) k32[q] = 0x7FFFFFFFu;
         wave_sync();
         // rank inside the group by the 31-bit key: a < b is the sign of a - b (both below
         // 2^31), so the comparisons are independent integer operations
@@ -1218,19 +1266,15 @@ k_element_wave(ElementArgs<R> a, int n_below, int last)
         int rk[PPL];
 #pragma unroll
         for (int r = 0; r < PPL; ++r) rk[r] = 0;
-        if (l == 0) {
-            rank_full<PPL>(k32, n8, m32, rk, (n + 63) >> 6);
-        } else {
 #pragma unroll
-            for (int r = 0; r < PPL; ++r)
-                if (lane + 64 * r < n) {
-                    int q = lo[r];
-                    for (; q + 4 <= hi[r]; q += 4)
-                        rk[r] += lt(k32[q], m32[r]) + lt(k32[q + 1], m32[r]) + lt(k32[q + 2], m32[r]) +
-                                 lt(k32[q + 3], m32[r]);
-                    for (; q < hi[r]; ++q) rk[r] += lt(k32[q], m32[r]);
-                }
-        }
+        for (int r = 0; r < PPL; ++r)
+            if (lane + 64 * r < n) {
+                int q = lo[r];
+                for (; q + 4 <= hi[r]; q += 4)
+                    rk[r] += lt(k32[q], m32[r]) + lt(k32[q + 1], m32[r]) + lt(k32[q + 2], m32[r]) +
+                             lt(k32[q + 3], m32[r]);
+                for (; q < hi[r]; ++q) rk[r] += lt(k32[q], m32[r]);
+            }
         // equal keys give equal ranks: detect by claiming the slots, then rank exactly
         // by (key, pid) in that case
 #pragma unroll
