@@ -76,14 +76,21 @@ void fem_set_fixed(const double* xfix, const uint16_t* fixed, int64_t nn, double
 void fem_csr_apply_dot(const int32_t* row_ptr, const int32_t* col, const double* val, const double* x, int64_t nn,
                        double* y, double* partial, int nblocks, hipStream_t s);
 int fem_csr_blocks(int64_t nn);
-// CG steps of one component with fused reductions (partial sums per block, then one block):
-// alpha = rz / pAp from the partials of p.Ap; x += alpha p, r -= alpha Ap, z = r / diag with
-// the partials of r.z and r.r; beta = rz_new / rz (rz <- rz_new, rr stored); p = z + beta p.
-// Scalars sc = [rz][pAp][rz_new][rr][alpha][beta].
-void fem_cg1_alpha(const double* partial, int nblocks, double* sc, hipStream_t s);
-void fem_cg1_xr_dot(const double* sc, const double* p, const double* Ap, const double* diag, int64_t nn, double* x,
-                    double* r, double* z, double* partial, int nblocks, hipStream_t s);
-void fem_cg1_beta(const double* partial, int nblocks, double* sc, hipStream_t s);
+// CG of one component in two launches per iteration on CG2_BLOCKS workgroups, whose
+// reductions are CG2_BLOCKS partials summed again by every workgroup of the next launch
+// in one fixed order.  Iteration k: fem_cg2_apply forms beta from the r.z partials
+// (part_rz, pairs r.z, r.r per workgroup) and r.z of iteration k - 1 (sc[(k + 1) & 1];
+// beta = 0 at k = 0), stores r.z in sc[k & 1], p_k = z + beta p_(k-1) from pold into pnew,
+// y = K p_k and the partials of p_k . y (part_py); fem_cg2_update forms alpha and updates
+// x, r and z = r / diag with the new r.z and r.r partials.  fem_cg2_dots gives the first
+// r.z, r.r partials.
+constexpr int CG2_BLOCKS = 1024;
+void fem_cg2_apply(const int32_t* row_ptr, const int32_t* col, const double* val, const double* z, const double* pold,
+                   double* pnew, int64_t nn, double* y, const double* part_rz, double* part_py, double* sc, int k,
+                   hipStream_t s);
+void fem_cg2_update(const double* sc, const double* part_py, const double* p, const double* y, const double* diag,
+                    int64_t nn, double* x, double* r, double* z, double* part_rz, int k, hipStream_t s);
+void fem_cg2_dots(const double* r, const double* z, int64_t nn, double* part_rz, hipStream_t s);
 // diag of the CSR matrix
 void fem_csr_diag(const int32_t* row_ptr, const int32_t* col, const double* val, int64_t nn, double* d,
                   hipStream_t s);

@@ -514,51 +514,93 @@ __device__ __forceinline__ double finish_sum(const double* partial, int nb, int 
     return v;
 }
 
-__global__ void __launch_bounds__(256) k_cg1_alpha(const double* __restrict__ partial, int nb, double* __restrict__ sc)
+// CG in two launches per iteration on CG2_BLOCKS workgroups (grid-stride rows): each
+// workgroup sums the CG2_BLOCKS partials of the launch before in the same fixed order, so
+// the scalars need no launch of their own; p is updated on the fly inside the product.
+// Scalars: sc[0], sc[1] hold r.z of alternate iterations.
+__device__ __forceinline__ double finish_cg2(const double* __restrict__ partial, int stride, int o, double* red)
 {
-    __shared__ double red[4];
-    const double pap = finish_sum(partial, nb, 1, 0, red);
-    if (threadIdx.x == 0) {
-        sc[1] = pap;
-        sc[4] = pap > 0.0 ? sc[0] / pap : 0.0;
-    }
-}
-
-__global__ void __launch_bounds__(256) k_cg1_xr_dot(const double* __restrict__ sc, const double* __restrict__ p,
-                                                    const double* __restrict__ Ap, const double* __restrict__ diag,
-                                                    int64_t nn, double* __restrict__ x, double* __restrict__ r,
-                                                    double* __restrict__ z, double* __restrict__ partial)
-{
-    __shared__ double red[4];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double rz = 0.0, rr = 0.0;
-    if (i < nn) {
-        const double al = sc[4];
-        x[i] += al * p[i];
-        const double ri = r[i] - al * Ap[i];
-        const double zi = ri / diag[i];
-        r[i] = ri;
-        z[i] = zi;
-        rz = ri * zi;
-        rr = ri * ri;
-    }
-    block_partial(rz, red, partial + 2 * blockIdx.x);
+    double t = 0.0;
+    for (int q = threadIdx.x; q < CG2_BLOCKS; q += 256) t += partial[q * stride + o];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    t = wave_sum_double(t);
+    if (lane == 0) red[w] = t;
     __syncthreads();
-    block_partial(rr, red, partial + 2 * blockIdx.x + 1);
+    const double v = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return v;
 }
 
-__global__ void __launch_bounds__(256) k_cg1_beta(const double* __restrict__ partial, int nb, double* __restrict__ sc)
+// iteration k: beta = (r.z now) / (r.z of iteration k - 1) (0 at k = 0), p_k = z + beta
+// p_(k-1) read from pold and written to pnew for the own rows, y = K p_k and the
+// partials of p_k . y
+__global__ void __launch_bounds__(256) k_cg2_apply(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                                   const double* __restrict__ val, const double* __restrict__ z,
+                                                   const double* __restrict__ pold, double* __restrict__ pnew,
+                                                   int64_t nn, double* __restrict__ y,
+                                                   const double* __restrict__ part_rz, double* __restrict__ part_py,
+                                                   double* __restrict__ sc, int k)
 {
     __shared__ double red[4];
-    const double rzn = finish_sum(partial, nb, 2, 0, red);
-    const double rr = finish_sum(partial, nb, 2, 1, red);
-    if (threadIdx.x == 0) {
-        const double rz = sc[0];
-        sc[5] = rz > 0.0 ? rzn / rz : 0.0;
-        sc[0] = rzn;
-        sc[2] = rzn;
-        sc[3] = rr;
+    const double rz = finish_cg2(part_rz, 2, 0, red);
+    const double rz_prev = sc[(k + 1) & 1];
+    const double beta = (k > 0 && rz_prev > 0.0) ? rz / rz_prev : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[k & 1] = rz;
+    double pq = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < nn; n += (int64_t)gridDim.x * 256) {
+        double acc = 0.0;
+        for (int32_t j = row_ptr[n]; j < row_ptr[n + 1]; ++j) {
+            const int32_t c = col[j];
+            acc += val[j] * (z[c] + beta * pold[c]);
+        }
+        const double pn = z[n] + beta * pold[n];
+        pnew[n] = pn;
+        y[n] = acc;
+        pq += pn * acc;
     }
+    block_partial(pq, red, part_py + blockIdx.x);
+}
+
+// iteration k: alpha = (r.z) / (p . K p); x += alpha p, r -= alpha K p, z = r / diag, and
+// the partials of r.z and r.r
+__global__ void __launch_bounds__(256) k_cg2_update(const double* __restrict__ sc, const double* __restrict__ part_py,
+                                                    const double* __restrict__ p, const double* __restrict__ y,
+                                                    const double* __restrict__ diag, int64_t nn, double* __restrict__ x,
+                                                    double* __restrict__ r, double* __restrict__ z,
+                                                    double* __restrict__ part_rz, int k)
+{
+    __shared__ double red[4];
+    const double pap = finish_cg2(part_py, 1, 0, red);
+    const double rz = sc[k & 1];
+    const double al = pap > 0.0 ? rz / pap : 0.0;
+    double rzl = 0.0, rrl = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < nn; n += (int64_t)gridDim.x * 256) {
+        x[n] += al * p[n];
+        const double ri = r[n] - al * y[n];
+        const double zi = ri / diag[n];
+        r[n] = ri;
+        z[n] = zi;
+        rzl += ri * zi;
+        rrl += ri * ri;
+    }
+    block_partial(rzl, red, part_rz + 2 * blockIdx.x);
+    __syncthreads();
+    block_partial(rrl, red, part_rz + 2 * blockIdx.x + 1);
+}
+
+// partials of r.z and r.r in the layout of k_cg2_update
+__global__ void __launch_bounds__(256) k_cg2_dots(const double* __restrict__ r, const double* __restrict__ z, int64_t nn,
+                                                  double* __restrict__ part_rz)
+{
+    __shared__ double red[4];
+    double rzl = 0.0, rrl = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < nn; n += (int64_t)gridDim.x * 256) {
+        rzl += r[n] * z[n];
+        rrl += r[n] * r[n];
+    }
+    block_partial(rzl, red, part_rz + 2 * blockIdx.x);
+    __syncthreads();
+    block_partial(rrl, red, part_rz + 2 * blockIdx.x + 1);
 }
 
 }  // namespace
@@ -573,18 +615,22 @@ void fem_csr_diag(const int32_t* row_ptr, const int32_t* col, const double* val,
 {
     if (nn > 0) hipLaunchKernelGGL(k_csr_diag, dim3(blocks(nn, 256)), dim3(256), 0, s, row_ptr, col, val, nn, d);
 }
-void fem_cg1_alpha(const double* partial, int nblocks, double* sc, hipStream_t s)
+void fem_cg2_apply(const int32_t* row_ptr, const int32_t* col, const double* val, const double* z, const double* pold,
+                   double* pnew, int64_t nn, double* y, const double* part_rz, double* part_py, double* sc, int k,
+                   hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg1_alpha, dim3(1), dim3(256), 0, s, partial, nblocks, sc);
+    hipLaunchKernelGGL(k_cg2_apply, dim3(CG2_BLOCKS), dim3(256), 0, s, row_ptr, col, val, z, pold, pnew, nn, y, part_rz,
+                       part_py, sc, k);
 }
-void fem_cg1_xr_dot(const double* sc, const double* p, const double* Ap, const double* diag, int64_t nn, double* x,
-                    double* r, double* z, double* partial, int nblocks, hipStream_t s)
+void fem_cg2_update(const double* sc, const double* part_py, const double* p, const double* y, const double* diag,
+                    int64_t nn, double* x, double* r, double* z, double* part_rz, int k, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg1_xr_dot, dim3(nblocks), dim3(256), 0, s, sc, p, Ap, diag, nn, x, r, z, partial);
+    hipLaunchKernelGGL(k_cg2_update, dim3(CG2_BLOCKS), dim3(256), 0, s, sc, part_py, p, y, diag, nn, x, r, z, part_rz,
+                       k);
 }
-void fem_cg1_beta(const double* partial, int nblocks, double* sc, hipStream_t s)
+void fem_cg2_dots(const double* r, const double* z, int64_t nn, double* part_rz, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg1_beta, dim3(1), dim3(256), 0, s, partial, nblocks, sc);
+    hipLaunchKernelGGL(k_cg2_dots, dim3(CG2_BLOCKS), dim3(256), 0, s, r, z, nn, part_rz);
 }
 
 void fem_store_wp(const double* wp9, int64_t nn, double* node, hipStream_t s)

@@ -794,28 +794,45 @@ pdf_status fem_cg_csr(pdf_ens_s* E, const double* b, double tol, int32_t max_ite
     FemState& F = E->fem;
     const int64_t nn = E->dg.nn;
     const int nb = fem_csr_blocks(nn);
+    // two p buffers (the vectors hold nine components' room), partials of r.z, r.r and
+    // of p.Kp, and the two r.z slots
+    double* pbuf[2] = {F.p, F.p + nn};
+    static_assert(3 * CG2_BLOCKS <= FEM_RED_BLOCKS * 18, "CG partials fit the reduction buffer");
+    double* part_rz = F.partial;
+    double* part_py = F.partial + 2 * CG2_BLOCKS;
     launch_fill_u64(reinterpret_cast<unsigned long long*>(F.sc), 6, 0ull, s);
+    launch_fill_u64(reinterpret_cast<unsigned long long*>(pbuf[1]), nn, 0ull, s);
     fem_csr_diag(F.csr_rp, F.csr_col, F.csr_val, nn, F.diag, s);
     fem_csr_apply_dot(F.csr_rp, F.csr_col, F.csr_val, F.x, nn, F.Ap, F.partial2, nb, s);
     fem_cg_init<1>(b, F.Ap, F.diag, F.nofix, nn, F.r, F.z, F.p, s);
-    fem_dot<1>(F.r, F.z, F.r, F.r, nn, F.partial, F.sc + 2, s);
-    fem_cg_beta<1>(F.sc, s);
-    double rr0 = 0.0, h[2];
-    HIP_TRY(hipMemcpyAsync(&rr0, F.sc + 3, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    fem_cg2_dots(F.r, F.z, nn, part_rz, s);
+    std::vector<double> h(2 * CG2_BLOCKS);
+    // r.r from the partials, in the same fixed order on the host
+    auto rr_sum = [&]() -> pdf_status {
+        HIP_TRY(hipMemcpyAsync(h.data(), part_rz, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return PDF_OK;
+    };
+    auto rr_of = [&]() {
+        double t = 0.0;
+        for (int q = 0; q < CG2_BLOCKS; ++q) t += h[2 * q + 1];
+        return t;
+    };
+    pdf_status st = rr_sum();
+    if (st != PDF_OK) return st;
+    const double rr0 = rr_of();
     int32_t it = 0;
     if (rr0 > 0.0) {
         while (it < max_iter) {
-            fem_csr_apply_dot(F.csr_rp, F.csr_col, F.csr_val, F.p, nn, F.Ap, F.partial2, nb, s);
-            fem_cg1_alpha(F.partial2, nb, F.sc, s);
-            fem_cg1_xr_dot(F.sc, F.p, F.Ap, F.diag, nn, F.x, F.r, F.z, F.partial2, nb, s);
-            fem_cg1_beta(F.partial2, nb, F.sc, s);
-            fem_cg_p<1>(F.sc, F.z, nn, F.p, s);
+            const int k = it;
+            fem_cg2_apply(F.csr_rp, F.csr_col, F.csr_val, F.z, pbuf[(k + 1) & 1], pbuf[k & 1], nn, F.Ap, part_rz,
+                          part_py, F.sc, k, s);
+            fem_cg2_update(F.sc, part_py, pbuf[k & 1], F.Ap, F.diag, nn, F.x, F.r, F.z, part_rz, k, s);
             ++it;
             if (it % 16 == 0 || it == max_iter) {
-                HIP_TRY(hipMemcpyAsync(h, F.sc + 2, sizeof(h), hipMemcpyDeviceToHost, s));
-                HIP_TRY(hipStreamSynchronize(s));
-                if (!(h[1] > tol * tol * rr0)) break;
+                st = rr_sum();
+                if (st != PDF_OK) return st;
+                if (!(rr_of() > tol * tol * rr0)) break;
             }
         }
     }

@@ -96,6 +96,36 @@ def test_control_parity(gpu):
     compare_stats(ge.stats(), oe.stats(), _skip_nodes(mesh, excl))
 
 
+def test_control_sets_the_element_tiers(gpu):
+    """200 per element merged down to at most 128 by control: the element pass then runs a
+    first wavefront tier of two particles per lane (n <= 128) and the set-up tier of five
+    for the elements the next step pushes above; both tiers are populated every step."""
+    _say("test_control_sets_the_element_tiers")
+    mesh = W.channel_mesh(10, 12, stretch=1.1 ** 8, seed=31)
+    f = W.channel_fields(mesh)
+    mo = W.model_constants()
+    ini = W.init_desc(ppe=200, bins=(4, 2, 2), src_x=3.0, src_r=0.4)
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    excl = set()
+    for n in range(4):
+        oe.step(5e-3)
+        ge.step(5e-3)
+        ref = oe.export()
+        rep, excl = compare_states(ge.export(), ref, frame, _length(mesh), excl)
+        counts = np.bincount(ref["elem"], minlength=mesh.n_elems)
+        if n > 0:
+            assert (counts > 128).any() and (counts <= 128).any(), counts
+        ro = oe.control(100, 128)
+        rg = ge.control(100, 128)
+        assert ro == {k: rg[k] for k in ro}, (ro, rg)
+    oe.step(5e-3)
+    ge.step(5e-3)
+    rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+    compare_stats(ge.stats(), oe.stats(), _skip_nodes(mesh, excl))
+    assert len(excl) <= 4
+
+
 def test_walls_slip_and_multistep_walks(gpu):
     """Tiny jittered box with large steps: multi-element walks, free-slip reflections,
     periodic seam; element ids must equal the oracle's."""
