@@ -4,10 +4,9 @@
 //
 // The operators are applied matrix-free by node gather: row n sums, over the elements
 // around n (the node->element lists of the grid), the element matrices
-// mass * M_e + L^2_e K_e built in registers from the element's frame coordinates
-// (K_e = A_e grad N_a . grad N_b, M_e = A_e (1 + delta_ab) / 12), so every row is owned by
-// one thread, the sums run in a fixed order, and no assembled matrix has to be rebuilt
-// when L^2 changes.  Vectors hold NC components per node ([nn][NC]); the components are
+// mass * M_e + L^2_e K_e formed from the element's stored K_e = A_e grad N_a . grad N_b and
+// A_e / 12 (M_e = A_e (1 + delta_ab) / 12), so every row is owned by one thread, the sums
+// run in a fixed order, and no assembled matrix has to be rebuilt when L^2 changes.  Vectors hold NC components per node ([nn][NC]); the components are
 // independent systems that share the element reads.
 #pragma once
 #include "pdf_impl.h"
@@ -18,6 +17,7 @@ constexpr int FEM_RED_BLOCKS = 256;   // partial sums of the reductions
 
 struct FemOp {
     const ElemGeo* geo;
+    const double* ke;     // [ne][8] element matrices of fem_elem_matrices
     const int64_t* n2e_ptr;
     const int32_t* n2e;
     int64_t nn;
@@ -29,6 +29,11 @@ struct FemOp {
                            // flags are read without a branch
 };
 
+// per element, from its frame coordinates: A_e grad N_a . grad N_b for (a, b) = (0, 0),
+// (1, 1), (2, 2), (0, 1), (0, 2), (1, 2) (Eqs. 39-40), then A_e / 12 (the mass matrix is
+// A_e (1 + delta_ab) / 12) and one unused slot; the grid's geometry never changes, so this
+// is done once
+void fem_elem_matrices(const ElemGeo* geo, int64_t ne, double* ke, hipStream_t s);
 template <int NC>
 void fem_apply(const FemOp& op, const double* x, double* y, hipStream_t s);
 template <int NC>

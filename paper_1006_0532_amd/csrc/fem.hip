@@ -21,6 +21,25 @@ __device__ __forceinline__ void p1_grad(const ElemGeo& G, double (&bx)[3], doubl
     }
 }
 
+__global__ void __launch_bounds__(256) k_fem_elem_matrices(const ElemGeo* __restrict__ geo, int64_t ne,
+                                                           double* __restrict__ ke)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= ne) return;
+    const ElemGeo& G = geo[e];
+    double bx[3], by[3];
+    p1_grad(G, bx, by);
+    double* k = ke + e * 8;
+    k[0] = G.area * (bx[0] * bx[0] + by[0] * by[0]);
+    k[1] = G.area * (bx[1] * bx[1] + by[1] * by[1]);
+    k[2] = G.area * (bx[2] * bx[2] + by[2] * by[2]);
+    k[3] = G.area * (bx[0] * bx[1] + by[0] * by[1]);
+    k[4] = G.area * (bx[0] * bx[2] + by[0] * by[2]);
+    k[5] = G.area * (bx[1] * bx[2] + by[1] * by[2]);
+    k[6] = G.area / 12.0;
+    k[7] = 0.0;
+}
+
 // row n of (mass M + stiff L^2 K) x, or its diagonal (x unused); Dirichlet rows give 0
 // (diagonal: 1)
 template <int NC>
@@ -36,16 +55,16 @@ __global__ void __launch_bounds__(256) k_fem_apply(FemOp op, const double* x, do
         const int64_t e = v / 3;
         const int a = v - 3 * (int)e;
         const ElemGeo& G = op.geo[e];
-        double bx[3], by[3];
-        p1_grad(G, bx, by);
+        const double* K = op.ke + e * 8;
         double l2[4] = {1.0, 1.0, 1.0, 1.0};
         if (op.L2)
 #pragma unroll
             for (int q = 0; q < 4; ++q) l2[q] = op.L2[e * 4 + q];
         for (int b = 0; b < 3; ++b) {
             if (diag_only && b != a) continue;
-            const double kab = G.area * (bx[a] * bx[b] + by[a] * by[b]);
-            const double mab = G.area * (a == b ? 2.0 : 1.0) / 12.0;
+            // (a, b) -> slot: diagonal a; (0, 1), (0, 2), (1, 2) -> 3, 4, 5
+            const double kab = K[a == b ? a : a + b + 2];
+            const double mab = K[6] * (a == b ? 2.0 : 1.0);
             const int64_t nb = G.node[b];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
@@ -92,14 +111,23 @@ __global__ void __launch_bounds__(256) k_fem_dot(const double* __restrict__ a, c
     }
 }
 
-__global__ void k_fem_dot_finish(const double* __restrict__ partial, int nb, int nq, int nout,
-                                 double* __restrict__ out)
+// out[q] = sum over the nb partials of component q (q < nout <= 18): a workgroup of 256
+// sums them in one fixed order (strided per thread, then the wavefronts, then the four
+// wavefront sums), so the loads are in flight together
+__global__ void __launch_bounds__(256) k_fem_dot_finish(const double* __restrict__ partial, int nb, int nq, int nout,
+                                                        double* __restrict__ out)
 {
+    __shared__ double red[4][18];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int q = 0; q < nout; ++q) {
+        double t = 0.0;
+        for (int k = threadIdx.x; k < nb; k += 256) t += partial[(int64_t)k * nq + q];
+        t = wave_sum_double(t);
+        if (lane == 0) red[w][q] = t;
+    }
+    __syncthreads();
     const int q = threadIdx.x;
-    if (q >= nout) return;
-    double t = 0.0;
-    for (int k = 0; k < nb; ++k) t += partial[(int64_t)k * nq + q];
-    out[q] = t;
+    if (q < nout) out[q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
 }
 
 template <int NC>
@@ -646,6 +674,11 @@ void fem_nearest_wall(const ElemGeo* geo, int64_t ne, const double* edges, int32
                            enrm);
 }
 
+void fem_elem_matrices(const ElemGeo* geo, int64_t ne, double* ke, hipStream_t s)
+{
+    if (ne > 0) hipLaunchKernelGGL(k_fem_elem_matrices, dim3(blocks(ne, 256)), dim3(256), 0, s, geo, ne, ke);
+}
+
 template <int NC>
 void fem_apply(const FemOp& op, const double* x, double* y, hipStream_t s)
 {
@@ -662,7 +695,8 @@ void fem_dot(const double* a, const double* b, const double* a2, const double* b
              double* out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fem_dot<NC>, dim3(FEM_RED_BLOCKS), dim3(256), 0, s, a, b, a2, b2, nn, partial);
-    hipLaunchKernelGGL(k_fem_dot_finish, dim3(1), dim3(64), 0, s, partial, FEM_RED_BLOCKS, 2 * NC,
+    static_assert(2 * NC <= 18, "at most 18 sums");
+    hipLaunchKernelGGL(k_fem_dot_finish, dim3(1), dim3(256), 0, s, partial, FEM_RED_BLOCKS, 2 * NC,
                        a2 ? 2 * NC : NC, out);
 }
 template <int NC>

@@ -640,7 +640,9 @@ pdf_status fem_geometry(pdf_ens_s* E, hipStream_t s)
     pdf_status st = fem_alloc(F.wkind, nn);
     if (st == PDF_OK) st = fem_alloc(F.wnrm, 2 * nn);
     if (st == PDF_OK) st = fem_alloc(F.enrm, 2 * ne);
+    if (st == PDF_OK) st = fem_alloc(F.ke, 8 * ne);
     if (st != PDF_OK) return st;
+    fem_elem_matrices(E->dg.geo, ne, F.ke, s);
     const int32_t nw = (int32_t)(edges.size() / 4);
     double* d_edges = nullptr;
     st = dalloc(&d_edges, 4 * (int64_t)std::max<int32_t>(nw, 1));
@@ -845,6 +847,7 @@ FemOp fem_op(pdf_ens_s* E, double mass, double stiff, const double* L2, const ui
 {
     FemOp op{};
     op.geo = E->dg.geo;
+    op.ke = E->fem.ke;
     op.n2e_ptr = E->dg.n2e_ptr;
     op.n2e = E->dg.n2e;
     op.nn = E->dg.nn;
@@ -1061,7 +1064,7 @@ pdf_status pdf_ens_destroy(pdf_ens E)
     dfree(E->fb_h);
     dfree(E->redist_plan);
     FemState& F = E->fem;
-    dfree(F.wkind); dfree(F.wnrm); dfree(F.enrm); dfree(F.f); dfree(F.xfix); dfree(F.b); dfree(F.x); dfree(F.r);
+    dfree(F.wkind); dfree(F.wnrm); dfree(F.enrm); dfree(F.ke); dfree(F.f); dfree(F.xfix); dfree(F.b); dfree(F.x); dfree(F.r);
     dfree(F.z); dfree(F.p); dfree(F.Ap); dfree(F.diag); dfree(F.fixed); dfree(F.nofix); dfree(F.L2); dfree(F.sc);
     dfree(F.partial);
     dfree(F.P); dfree(F.gp0); dfree(F.gP); dfree(F.gdP);

@@ -135,6 +135,7 @@ struct FemState {
     uint8_t* wkind = nullptr;     // [nn] 0 interior, 1 free-slip node, 2 no-slip node
     double* wnrm = nullptr;       // [nn][2] outward wall normal of no-slip nodes
     double* enrm = nullptr;       // [ne][2] normal of the nearest no-slip wall edge
+    double* ke = nullptr;         // [ne][8] element matrices (see fem.h)
     double *f = nullptr, *xfix = nullptr, *b = nullptr, *x = nullptr;        // [nn][9]
     double *r = nullptr, *z = nullptr, *p = nullptr, *Ap = nullptr, *diag = nullptr;
     uint16_t* fixed = nullptr;    // [nn] Dirichlet bits of the nine components
