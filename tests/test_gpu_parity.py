@@ -126,6 +126,63 @@ def test_control_sets_the_element_tiers(gpu):
     assert len(excl) <= 4
 
 
+def _adversarial_velocities(st, seed=5):
+    """Velocity sets that stress the element sort, by element id mod 5: all equal (ties
+    by pid at every level); U1 of both signed zeros and the smallest subnormals; a
+    Gaussian with one outlier a million times larger; U1 a run of consecutive doubles
+    above 1; U1 half 0, half the smallest subnormal (a span whose reciprocal overflows)."""
+    rng = np.random.default_rng(seed)
+    u = st["u"].copy()
+    tiny = np.nextafter(0.0, 1.0)
+    for e in np.unique(st["elem"]):
+        idx = np.nonzero(st["elem"] == e)[0]
+        n = len(idx)
+        kind = int(e) % 5
+        if kind == 0:
+            u[idx] = (0.25, -0.125, 0.5)
+        elif kind == 1:
+            u[idx, 0] = np.resize([-0.0, 0.0, tiny, -tiny, 1e-300, -1e-300], n)
+            u[idx, 1:] = rng.normal(0.0, 0.05, (n, 2))
+        elif kind == 2:
+            u[idx] = rng.normal(0.0, 0.05, (n, 3))
+            u[idx[n // 2], 0] = 1e6
+        elif kind == 3:
+            v = 1.0
+            for j in rng.permutation(n):
+                u[idx[j], 0] = v
+                v = np.nextafter(v, 2.0)
+            u[idx, 1] = np.resize([0.1, 0.2], n)
+        else:
+            u[idx, 0] = np.where(np.arange(n) % 2 == 0, 0.0, tiny)
+    return u
+
+
+@pytest.mark.parametrize("conditioning", [0, 1])
+def test_element_sort_on_adversarial_velocities(gpu, conditioning):
+    """Bins seen through number control (merges pair particles of one bin): imported
+    states whose velocities tie, straddle zero, hold an outlier or span a few ulps give
+    the oracle's merges, under the sort-and-divide bins and under Fox's projection."""
+    _say(f"test_element_sort_on_adversarial_velocities conditioning={conditioning}")
+    mesh = box(4, 4, length=2.0, jitter=0.1)
+    f = W.uniform_fields(mesh, mean_u=(0.3, 0.1, 0.0), mean_omega=4.0)
+    mo = W.model_constants()
+    ini = W.init_desc(ppe=100, bins=(4, 2, 2), src_x=1.0, src_r=0.4, conditioning=conditioning)
+    og = O.Grid(mesh, f, mo)
+    st = O.Ensemble(og, ini).export()
+    st["u"] = _adversarial_velocities(st)
+    oe = O.Ensemble(og, ini)
+    oe.import_state(st, step=0, next_pid=len(st["x"]))
+    gg = gpu.Grid(mesh, f, mo)
+    ge = gpu.Ensemble(gg, ini, capacity=200 * mesh.n_elems)
+    ge.import_state(st, step=0, next_pid=len(st["x"]))
+    frame = og.export()["frame"]
+    ro, rg = oe.control(40, 60), ge.control(40, 60)
+    assert ro == {k: rg[k] for k in ro}, (ro, rg)
+    assert rg["merged"] > 0
+    rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh))
+    assert not excl
+
+
 def test_walls_slip_and_multistep_walks(gpu):
     """Tiny jittered box with large steps: multi-element walks, free-slip reflections,
     periodic seam; element ids must equal the oracle's."""
