@@ -319,8 +319,10 @@ pdf_status pdf_elliptic_relaxation(pdf_ens ens, const pdf_elliptic_model* consts
  * average of those gradients around the node.  P (zero at the first call) accumulates dP;
  * the nodal mean-pressure gradient used by later steps becomes the set-up field plus the
  * nodal average of the element gradients of P; with statistics feedback on, the corrected
- * nodal mean velocity is fed back again.  Jacobi-preconditioned CG from zero to tol
- * relative residual or max_iter iterations.  dp_out (may be NULL) receives dP [nn];
+ * nodal mean velocity is fed back again.  CG from zero to tol relative residual or max_iter
+ * iterations, preconditioned by a smoothed-aggregation multigrid V-cycle built once per
+ * ensemble from the assembled matrix (Jacobi when its aggregation stalls); a grid of at
+ * most 400 nodes is solved by its dense coarse inverse alone.  dp_out (may be NULL) receives dP [nn];
  * *iters_out (may be NULL) the iterations.  Synchronises.
  * Errors: PDF_E_INVAL, PDF_E_STATE (a node without statistics), PDF_E_NOMEM, PDF_E_HIP. */
 pdf_status pdf_pressure_projection(pdf_ens ens, double dt, double cp, double tol, int32_t max_iter, double* dp_out,

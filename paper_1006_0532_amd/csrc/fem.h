@@ -96,6 +96,9 @@ void fem_cg2_apply(const int32_t* row_ptr, const int32_t* col, const double* val
 void fem_cg2_update(const double* sc, const double* part_py, const double* p, const double* y, const double* diag,
                     int64_t nn, double* x, double* r, double* z, double* part_rz, int k, hipStream_t s);
 void fem_cg2_dots(const double* r, const double* z, int64_t nn, double* part_rz, hipStream_t s);
+// the update of fem_cg2_update without z and partials, for a preconditioner applied after it
+void fem_cg2_update_xr(const double* sc, const double* part_py, const double* p, const double* y, int64_t nn,
+                       double* x, double* r, int k, hipStream_t s);
 // diag of the CSR matrix
 void fem_csr_diag(const int32_t* row_ptr, const int32_t* col, const double* val, int64_t nn, double* d,
                   hipStream_t s);

@@ -616,6 +616,23 @@ __global__ void __launch_bounds__(256) k_cg2_update(const double* __restrict__ s
     block_partial(rrl, red, part_rz + 2 * blockIdx.x + 1);
 }
 
+// iteration k with a preconditioner applied outside: alpha as in k_cg2_update; x += alpha p,
+// r -= alpha K p only
+__global__ void __launch_bounds__(256) k_cg2_update_xr(const double* __restrict__ sc,
+                                                       const double* __restrict__ part_py, const double* __restrict__ p,
+                                                       const double* __restrict__ y, int64_t nn,
+                                                       double* __restrict__ x, double* __restrict__ r, int k)
+{
+    __shared__ double red[4];
+    const double pap = finish_cg2(part_py, 1, 0, red);
+    const double rz = sc[k & 1];
+    const double al = pap > 0.0 ? rz / pap : 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < nn; n += (int64_t)gridDim.x * 256) {
+        x[n] += al * p[n];
+        r[n] -= al * y[n];
+    }
+}
+
 // partials of r.z and r.r in the layout of k_cg2_update
 __global__ void __launch_bounds__(256) k_cg2_dots(const double* __restrict__ r, const double* __restrict__ z, int64_t nn,
                                                   double* __restrict__ part_rz)
@@ -655,6 +672,11 @@ void fem_cg2_update(const double* sc, const double* part_py, const double* p, co
 {
     hipLaunchKernelGGL(k_cg2_update, dim3(CG2_BLOCKS), dim3(256), 0, s, sc, part_py, p, y, diag, nn, x, r, z, part_rz,
                        k);
+}
+void fem_cg2_update_xr(const double* sc, const double* part_py, const double* p, const double* y, int64_t nn,
+                       double* x, double* r, int k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg2_update_xr, dim3(CG2_BLOCKS), dim3(256), 0, s, sc, part_py, p, y, nn, x, r, k);
 }
 void fem_cg2_dots(const double* r, const double* z, int64_t nn, double* part_rz, hipStream_t s)
 {

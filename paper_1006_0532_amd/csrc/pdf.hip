@@ -787,6 +787,21 @@ pdf_status fem_pressure_matrix(pdf_ens_s* E, hipStream_t s)
     HIP_TRY(hipMemcpyAsync(F.csr_col, col.data(), sizeof(int32_t) * col.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(F.csr_val, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
+    // multigrid preconditioner of the same matrix (Jacobi when the hierarchy cannot be built)
+    HostCsr A;
+    A.n = A.m = nn;
+    A.rp = std::move(rp);
+    A.col = std::move(col);
+    A.val = std::move(val);
+    AmgHost h;
+    if (amg_build(A, h)) {
+        F.amg = new AmgDev();
+        if (amg_upload(h, *F.amg, s) != hipSuccess) {
+            (void)hipGetLastError();
+            delete F.amg;
+            F.amg = nullptr;
+        }
+    }
     return PDF_OK;
 }
 
@@ -820,6 +835,34 @@ pdf_status fem_cg_csr(pdf_ens_s* E, const double* b, double tol, int32_t max_ite
         for (int q = 0; q < CG2_BLOCKS; ++q) t += h[2 * q + 1];
         return t;
     };
+    if (F.amg) {
+        // preconditioned by the multigrid V-cycle: z = M^-1 r after every update
+        amg_vcycle(*F.amg, F.r, F.z, s);
+        fem_cg2_dots(F.r, F.z, nn, part_rz, s);
+        pdf_status st = rr_sum();
+        if (st != PDF_OK) return st;
+        const double rr0 = rr_of();
+        int32_t it = 0;
+        if (rr0 > 0.0) {
+            while (it < max_iter) {
+                const int k = it;
+                fem_cg2_apply(F.csr_rp, F.csr_col, F.csr_val, F.z, pbuf[(k + 1) & 1], pbuf[k & 1], nn, F.Ap, part_rz,
+                              part_py, F.sc, k, s);
+                fem_cg2_update_xr(F.sc, part_py, pbuf[k & 1], F.Ap, nn, F.x, F.r, k, s);
+                amg_vcycle(*F.amg, F.r, F.z, s);
+                fem_cg2_dots(F.r, F.z, nn, part_rz, s);
+                ++it;
+                if (it % 2 == 0 || it == max_iter) {
+                    st = rr_sum();
+                    if (st != PDF_OK) return st;
+                    if (!(rr_of() > tol * tol * rr0)) break;
+                }
+            }
+        }
+        HIP_TRY(hipGetLastError());
+        if (iters) *iters = it;
+        return PDF_OK;
+    }
     pdf_status st = rr_sum();
     if (st != PDF_OK) return st;
     const double rr0 = rr_of();
@@ -1069,6 +1112,11 @@ pdf_status pdf_ens_destroy(pdf_ens E)
     dfree(F.partial);
     dfree(F.P); dfree(F.gp0); dfree(F.gP); dfree(F.gdP);
     dfree(F.csr_rp); dfree(F.csr_col); dfree(F.csr_val); dfree(F.partial2);
+    if (F.amg) {
+        amg_free(*F.amg);
+        delete F.amg;
+        F.amg = nullptr;
+    }
     delete E;
     return PDF_OK;
 }

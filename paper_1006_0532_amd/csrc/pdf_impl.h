@@ -1,5 +1,6 @@
 // Internal types of libpdfgpu: device data layout and host-side handles.
 #pragma once
+#include "amg.h"
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -147,6 +148,7 @@ struct FemState {
     int32_t *csr_rp = nullptr, *csr_col = nullptr;   // assembled stiffness matrix of the grid
     double* csr_val = nullptr;
     double* partial2 = nullptr;   // block partials of the assembled-matrix CG
+    pdfgpu::AmgDev* amg = nullptr;   // multigrid preconditioner of that CG (null: Jacobi)
     double *P = nullptr, *gp0 = nullptr, *gP = nullptr, *gdP = nullptr;       // [nn], [nn][2], [ne][2]
 };
 
