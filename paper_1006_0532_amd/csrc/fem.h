@@ -27,7 +27,17 @@ struct FemOp {
     const uint16_t* fixed; // [nn] bit c: component c of the node is a Dirichlet entry (its row
                            // gives 0); never null (an all-zero mask for none), so that the
                            // flags are read without a branch
+    // assembled form of the nine-component operator (null: matrix-free): the grid's CSR
+    // pattern and four coefficient arrays [4][nnz] (L^2 of wp_11, wp_22, wp_33, off-diagonal)
+    const int32_t* crp = nullptr;
+    const int32_t* ccol = nullptr;
+    const double* cval = nullptr;
+    int64_t nnz = 0;
 };
+
+// cval [4][nnz] = mass M + stiff L^2_g K on the pattern (crp, ccol) of op, summed over the
+// elements around each row in the node->element order
+void fem_assemble4(const FemOp& op, double* cval, hipStream_t s);
 
 // per element, from its frame coordinates: A_e grad N_a . grad N_b for (a, b) = (0, 0),
 // (1, 1), (2, 2), (0, 1), (0, 2), (1, 2) (Eqs. 39-40), then A_e / 12 (the mass matrix is

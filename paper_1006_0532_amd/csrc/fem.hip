@@ -80,6 +80,59 @@ __global__ void __launch_bounds__(256) k_fem_apply(FemOp op, const double* x, do
     for (int c = 0; c < NC; ++c) y[n * NC + c] = ((fm >> c) & 1u) ? fixed_value : acc[c];
 }
 
+__global__ void __launch_bounds__(256) k_fem_assemble4(FemOp op, double* __restrict__ cval)
+{
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= op.nn) return;
+    const int32_t k0 = op.crp[n], k1 = op.crp[n + 1];
+    for (int32_t k = k0; k < k1; ++k)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) cval[g * op.nnz + k] = 0.0;
+    for (int64_t j = op.n2e_ptr[n]; j < op.n2e_ptr[n + 1]; ++j) {
+        const int32_t v = op.n2e[j];
+        const int64_t e = v / 3;
+        const int a = v - 3 * (int)e;
+        const double* K = op.ke + e * 8;
+        double l2[4] = {1.0, 1.0, 1.0, 1.0};
+        if (op.L2)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) l2[q] = op.L2[e * 4 + q];
+        for (int b = 0; b < 3; ++b) {
+            const int32_t nb = op.geo[e].node[b];
+            int32_t k = k0;
+            while (k < k1 - 1 && op.ccol[k] != nb) ++k;     // the row holds every vertex of its elements
+            const double kab = K[a == b ? a : a + b + 2];
+            const double mab = K[6] * (a == b ? 2.0 : 1.0);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) cval[g * op.nnz + k] += op.mass * mab + op.stiff * (l2[g] * kab);
+        }
+    }
+}
+
+// y = A x (diag_only: the diagonal) of the assembled nine-component operator, a thread per
+// (row, component); Dirichlet rows give 0 (diagonal: 1)
+__global__ void __launch_bounds__(256) k_fem_apply_csr9(FemOp op, const double* __restrict__ x,
+                                                        double* __restrict__ y, int diag_only)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= op.nn * 9) return;
+    const int64_t n = q / 9;
+    const int c = (int)(q - 9 * n);
+    const int g = c / 3 == c % 3 ? c / 3 : 3;
+    const double* __restrict__ v = op.cval + g * op.nnz;
+    double acc = 0.0;
+    for (int32_t k = op.crp[n]; k < op.crp[n + 1]; ++k) {
+        const int32_t j = op.ccol[k];
+        if (diag_only) {
+            if (j == n) acc = v[k];
+        } else {
+            acc += v[k] * x[(int64_t)j * 9 + c];
+        }
+    }
+    const bool fx = (op.fixed[n] >> c) & 1u;
+    y[q] = fx ? (diag_only ? 1.0 : 0.0) : acc;
+}
+
 template <int NC>
 __global__ void __launch_bounds__(256) k_fem_dot(const double* __restrict__ a, const double* __restrict__ b,
                                                  const double* __restrict__ a2, const double* __restrict__ b2,
@@ -701,15 +754,27 @@ void fem_elem_matrices(const ElemGeo* geo, int64_t ne, double* ke, hipStream_t s
     if (ne > 0) hipLaunchKernelGGL(k_fem_elem_matrices, dim3(blocks(ne, 256)), dim3(256), 0, s, geo, ne, ke);
 }
 
+void fem_assemble4(const FemOp& op, double* cval, hipStream_t s)
+{
+    if (op.nn > 0) hipLaunchKernelGGL(k_fem_assemble4, dim3(blocks(op.nn, 256)), dim3(256), 0, s, op, cval);
+}
+
 template <int NC>
 void fem_apply(const FemOp& op, const double* x, double* y, hipStream_t s)
 {
-    if (op.nn > 0) hipLaunchKernelGGL(k_fem_apply<NC>, dim3(blocks(op.nn, 256)), dim3(256), 0, s, op, x, y, 0);
+    if (op.nn <= 0) return;
+    if (NC == 9 && op.cval)
+        hipLaunchKernelGGL(k_fem_apply_csr9, dim3(blocks(op.nn * 9, 256)), dim3(256), 0, s, op, x, y, 0);
+    else
+        hipLaunchKernelGGL(k_fem_apply<NC>, dim3(blocks(op.nn, 256)), dim3(256), 0, s, op, x, y, 0);
 }
 template <int NC>
 void fem_diag(const FemOp& op, double* d, hipStream_t s)
 {
-    if (op.nn > 0)
+    if (op.nn <= 0) return;
+    if (NC == 9 && op.cval)
+        hipLaunchKernelGGL(k_fem_apply_csr9, dim3(blocks(op.nn * 9, 256)), dim3(256), 0, s, op, (const double*)d, d, 1);
+    else
         hipLaunchKernelGGL(k_fem_apply<NC>, dim3(blocks(op.nn, 256)), dim3(256), 0, s, op, (const double*)d, d, 1);
 }
 template <int NC>
@@ -770,6 +835,7 @@ void fem_mass_rhs(const FemOp& op, const double* f, double* b, hipStream_t s)
     FemOp m = op;
     m.mass = 1.0;
     m.stiff = 0.0;
+    m.cval = nullptr;
     fem_apply<9>(m, f, b, s);
 }
 void fem_set_fixed(const double* xfix, const uint16_t* fixed, int64_t nn, double* x, hipStream_t s)

@@ -787,22 +787,29 @@ pdf_status fem_pressure_matrix(pdf_ens_s* E, hipStream_t s)
     HIP_TRY(hipMemcpyAsync(F.csr_col, col.data(), sizeof(int32_t) * col.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(F.csr_val, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
-    // multigrid preconditioner of the same matrix (Jacobi when the hierarchy cannot be built)
-    HostCsr A;
-    A.n = A.m = nn;
-    A.rp = std::move(rp);
-    A.col = std::move(col);
-    A.val = std::move(val);
-    AmgHost h;
-    if (amg_build(A, h)) {
-        F.amg = new AmgDev();
-        if (amg_upload(h, *F.amg, s) != hipSuccess) {
-            (void)hipGetLastError();
-            delete F.amg;
-            F.amg = nullptr;
-        }
-    }
+    F.csr_nnz = (int64_t)col.size();
+    F.hcsr.n = F.hcsr.m = nn;
+    F.hcsr.rp = std::move(rp);
+    F.hcsr.col = std::move(col);
+    F.hcsr.val = std::move(val);
     return PDF_OK;
+}
+
+// multigrid preconditioner of the pressure matrix, built on first use (Jacobi when the
+// hierarchy cannot be built or uploaded)
+void fem_pressure_amg(pdf_ens_s* E, hipStream_t s)
+{
+    FemState& F = E->fem;
+    if (F.amg_tried) return;
+    F.amg_tried = true;
+    AmgHost h;
+    if (!amg_build(F.hcsr, h)) return;
+    F.amg = new AmgDev();
+    if (amg_upload(h, *F.amg, s) != hipSuccess) {
+        (void)hipGetLastError();
+        delete F.amg;
+        F.amg = nullptr;
+    }
 }
 
 // Jacobi-preconditioned CG on the assembled scalar matrix from x = 0, with fused reductions
@@ -1111,7 +1118,7 @@ pdf_status pdf_ens_destroy(pdf_ens E)
     dfree(F.z); dfree(F.p); dfree(F.Ap); dfree(F.diag); dfree(F.fixed); dfree(F.nofix); dfree(F.L2); dfree(F.sc);
     dfree(F.partial);
     dfree(F.P); dfree(F.gp0); dfree(F.gP); dfree(F.gdP);
-    dfree(F.csr_rp); dfree(F.csr_col); dfree(F.csr_val); dfree(F.partial2);
+    dfree(F.csr_rp); dfree(F.csr_col); dfree(F.csr_val); dfree(F.partial2); dfree(F.cval4);
     if (F.amg) {
         amg_free(*F.amg);
         delete F.amg;
@@ -1437,6 +1444,19 @@ pdf_status pdf_elliptic_relaxation(pdf_ens E, const pdf_elliptic_model* consts, 
                         F.fixed, F.L2, E->err, s);
     FemOp op = fem_op(E, 1.0, 1.0, F.L2, F.fixed);
     fem_mass_rhs(op, F.f, F.b, s);
+    // the operator on the grid's CSR pattern: assembled once per solve (L^2 changes with
+    // the statistics), then applied a thread per row and component
+    st = fem_pressure_matrix(E, s);
+    if (st != PDF_OK) return st;
+    if (!F.cval4) {
+        st = dalloc(&F.cval4, 4 * F.csr_nnz);
+        if (st != PDF_OK) return st;
+    }
+    op.crp = F.csr_rp;
+    op.ccol = F.csr_col;
+    op.nnz = F.csr_nnz;
+    fem_assemble4(op, F.cval4, s);
+    op.cval = F.cval4;
     launch_fill_u64(reinterpret_cast<unsigned long long*>(F.x), 9 * g.nn, 0ull, s);
     fem_set_fixed(F.xfix, F.fixed, g.nn, F.x, s);
     st = fem_cg<9>(E, op, F.b, tol, max_iter, iters_out, s);
@@ -1479,6 +1499,7 @@ pdf_status pdf_pressure_projection(pdf_ens E, double dt, double cp, double tol, 
     if (st == PDF_OK) st = fem_alloc(F.gP, 2 * ne);
     if (st == PDF_OK) st = fem_alloc(F.gdP, 2 * ne);
     if (st == PDF_OK) st = fem_pressure_matrix(E, s);
+    if (st == PDF_OK) fem_pressure_amg(E, s);
     if (st == PDF_OK) st = fem_check(E, s, "pdf_pressure_projection");
     if (st != PDF_OK) return st;
     if (!F.pressure) {

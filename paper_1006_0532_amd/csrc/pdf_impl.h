@@ -148,7 +148,11 @@ struct FemState {
     int32_t *csr_rp = nullptr, *csr_col = nullptr;   // assembled stiffness matrix of the grid
     double* csr_val = nullptr;
     double* partial2 = nullptr;   // block partials of the assembled-matrix CG
-    pdfgpu::AmgDev* amg = nullptr;   // multigrid preconditioner of that CG (null: Jacobi)
+    int64_t csr_nnz = 0;
+    pdfgpu::HostCsr hcsr;            // host copy of the assembled matrix (multigrid set-up)
+    double* cval4 = nullptr;         // [4][csr_nnz] assembled elliptic-relaxation operator
+    pdfgpu::AmgDev* amg = nullptr;   // multigrid preconditioner of the pressure CG (null: Jacobi)
+    bool amg_tried = false;
     double *P = nullptr, *gp0 = nullptr, *gP = nullptr, *gdP = nullptr;       // [nn], [nn][2], [ne][2]
 };
 
