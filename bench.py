@@ -82,6 +82,9 @@ def parse():
                    help="run only the large street canyon in the mixed form and print its figures")
     p.add_argument("--no-eulerian", action="store_true",
                    help="skip timing the elliptic-relaxation and pressure-projection solves")
+    p.add_argument("--eulerian-only", action="store_true",
+                   help="set up the channel, take the warm-up steps, then run only the Eulerian solves "
+                        "and the closed loop and print their figures")
     p.add_argument("--batched-problems", type=int, default=64)
     return p.parse_args()
 
@@ -278,6 +281,44 @@ def batched_form(args):
     return out
 
 
+def eulerian_leg(ens, dt, ctl):
+    """Eulerian solves of Sec. 3.2 on the ensemble (a first call sets up the boundary
+    geometry, work arrays, the assembled matrix and its multigrid hierarchy; the second is
+    timed, results copied to the host included), then the closed loop of Table 1 with
+    statistics feedback: Eq. (12) from the last statistics stored as the particles' wp, the
+    particle step with number control, the pressure projection with the correction of
+    Eq. (31), the fields fed back."""
+    import torch
+    eulerian = {}
+    for name, fn in (("elliptic_relaxation", lambda: ens.elliptic_relaxation(tol=1e-10)),
+                     ("pressure_projection", lambda: ens.pressure_projection(dt, cp=1e-3, tol=1e-10))):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, it = fn()
+        torch.cuda.synchronize()
+        eulerian[name] = {"ms": round(1e3 * (time.perf_counter() - t), 2), "cg_iterations": it, "tol": 1e-10}
+    ens.set_feedback(True, 1.0, feed_rey=True, feed_omega=True)
+
+    def loop_step():
+        ens.elliptic_relaxation(tol=1e-10, store=True)
+        ens.step(dt)
+        ens.control(*ctl)
+        ens.pressure_projection(dt, cp=1e-3, tol=1e-10)
+
+    loop_step()
+    ens.sync()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        loop_step()
+    ens.sync()
+    torch.cuda.synchronize()
+    eulerian["closed_loop_step"] = {"ms": round(1e3 * (time.perf_counter() - t) / 3, 2), "steps": 3,
+                                    "order": "elliptic relaxation, particle step, control, pressure projection"}
+    return eulerian
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -316,6 +357,9 @@ def main():
         ens.control(*ctl)
     ens.sync()
     torch.cuda.synchronize()
+    if args.eulerian_only:
+        print(json.dumps({"workload": "channel_large", "eulerian": eulerian_leg(ens, dt, ctl)}), flush=True)
+        return
 
     live = []
     ens.timing(True)
@@ -370,41 +414,10 @@ def main():
             per_kernel[k]["GB/s"] = round(bpp * mean_live / (avg * 1e-3) / 1e9, 1)
     print(f"[bench] per kernel: {json.dumps(per_kernel)}", file=sys.stderr, flush=True)
 
-    # Eulerian solves of Sec. 3.2 on the same ensemble after the timed steps (a first call
-    # sets up the boundary geometry and work arrays; the second is timed, results copied to
-    # the host included)
+    # Eulerian solves and the closed loop on the same ensemble after the timed steps
     eulerian = None
     if not args.no_eulerian:
-        eulerian = {}
-        for name, fn in (("elliptic_relaxation", lambda: ens.elliptic_relaxation(tol=1e-10)),
-                         ("pressure_projection", lambda: ens.pressure_projection(dt, cp=1e-3, tol=1e-10))):
-            fn()
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            _, it = fn()
-            torch.cuda.synchronize()
-            eulerian[name] = {"ms": round(1e3 * (time.perf_counter() - t), 2), "cg_iterations": it, "tol": 1e-10}
-        # the closed loop of Table 1 with statistics feedback: Eq. (12) from the last
-        # statistics stored as the particles' wp, the particle step with number control,
-        # the pressure projection with the correction of Eq. (31), the fields fed back
-        ens.set_feedback(True, 1.0, feed_rey=True, feed_omega=True)
-
-        def loop_step():
-            ens.elliptic_relaxation(tol=1e-10, store=True)
-            ens.step(dt)
-            ens.control(*ctl)
-            ens.pressure_projection(dt, cp=1e-3, tol=1e-10)
-
-        loop_step()
-        ens.sync()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(3):
-            loop_step()
-        ens.sync()
-        torch.cuda.synchronize()
-        eulerian["closed_loop_step"] = {"ms": round(1e3 * (time.perf_counter() - t) / 3, 2), "steps": 3,
-                                        "order": "elliptic relaxation, particle step, control, pressure projection"}
+        eulerian = eulerian_leg(ens, dt, ctl)
         print(f"[bench] eulerian: {json.dumps(eulerian)}", file=sys.stderr, flush=True)
 
     forms = None
