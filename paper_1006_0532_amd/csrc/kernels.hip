@@ -98,20 +98,20 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
                 const R* __restrict__ FA = a.node + (int64_t)Gu->node[0] * NODE_STRIDE;
                 const R* __restrict__ FB = a.node + (int64_t)Gu->node[1] * NODE_STRIDE;
                 const R* __restrict__ FC = a.node + (int64_t)Gu->node[2] * NODE_STRIDE;
-                // three groups of fields (7 each, or 8 with the nine-component wp); the
-                // empty asm statements keep the compiler from loading all node values into
-                // scalar registers at once.  Explicit fused multiply-adds fix the rounding
-                // whatever the operands' registers.
+                // fields in groups of eight (the last one shorter with the six-component wp);
+                // the empty asm statements keep the compiler from loading all node values
+                // into scalar registers at once (groups of 8 measured faster than 7 or 11).
+                // Explicit fused multiply-adds fix the rounding whatever the operands'
+                // registers.
                 auto ip = [&](int q) { return fma(lc, FC[q], fma(lb, FB[q], la * FA[q])); };
-                constexpr int G = WPFULL ? 8 : 7;
 #pragma unroll
-                for (int q = 0; q < G; ++q) f[q] = ip(q);
+                for (int q = 0; q < 8; ++q) f[q] = ip(q);
                 asm volatile("" ::: "memory");
 #pragma unroll
-                for (int q = G; q < 2 * G; ++q) f[q] = ip(q);
+                for (int q = 8; q < 16; ++q) f[q] = ip(q);
                 asm volatile("" ::: "memory");
 #pragma unroll
-                for (int q = 2 * G; q < 3 * G; ++q) f[q] = ip(q);
+                for (int q = 16; q < (WPFULL ? 24 : 21); ++q) f[q] = ip(q);
 #pragma unroll
                 for (int q = 0; q < 6; ++q) gu[q] = (R)Gu->gu[q];
             }
