@@ -46,9 +46,11 @@ def _cases():
     # 2 040 nodes: above the dense coarse size, so the pressure solve runs the multigrid
     # hierarchy (three levels and the dense coarsest)
     m2 = W.channel_mesh(40, 50, stretch=1.1 ** 8, seed=21)
+    m3 = W.cavity_mesh(20, 24, 24, seed=9)      # 2 004 nodes: walls, corners, a periodic channel
     return [("channel", m0, W.channel_fields(m0), W.init_desc(ppe=60, src_x=3.0, src_r=0.4)),
             ("cavity", m1, W.cavity_fields(m1), W.init_desc(ppe=60, src_x=1.5, src_y=0.5, src_r=0.2)),
-            ("channel_2040_nodes", m2, W.channel_fields(m2), W.init_desc(ppe=20, src_x=3.0, src_r=0.4))]
+            ("channel_2040_nodes", m2, W.channel_fields(m2), W.init_desc(ppe=20, src_x=3.0, src_r=0.4)),
+            ("cavity_2004_nodes", m3, W.cavity_fields(m3), W.init_desc(ppe=20, src_x=1.5, src_y=0.5, src_r=0.2))]
 
 
 @pytest.mark.parametrize("case", [0, 1])
@@ -68,7 +70,7 @@ def test_elliptic_relaxation_parity(gpu, case):
     assert np.abs(wp - ref).max() <= 1e-8 * scale, (np.abs(wp - ref).max(), scale)
 
 
-@pytest.mark.parametrize("case", [0, 1, 2])
+@pytest.mark.parametrize("case", [0, 1, 2, 3])
 def test_pressure_projection_parity(gpu, case):
     name, mesh, f, ini = _cases()[case]
     _say(f"test_pressure_projection_parity {name}")
