@@ -392,3 +392,36 @@ def test_large_cavity_mixed_against_fp64(gpu, name):
         assert r["cloned"] > 0 and r["merged"] > 0
     b.close()
     gg.close()
+
+
+def test_mixed_closed_loop(gpu):
+    """The Eulerian solves on a mixed ensemble: three closed-loop steps (Eq. 12 stored as
+    the particles' wp, a step, the pressure projection with the correction of Eq. 31, the
+    fields fed back) stay within the mixed form's bounds of the FP64 oracle's loop; the
+    solves read the FP64 statistics, so their results agree closely too."""
+    from oracle import fem
+    _say("test_mixed_closed_loop")
+    mesh = W.channel_mesh(16, 20, stretch=1.1 ** 8, seed=21)
+    f = W.channel_fields(mesh)
+    mo = W.model_constants()
+    ini = W.init_desc(ppe=60, src_x=3.0, src_r=0.4)
+    og = O.Grid(mesh, f, mo)
+    oe = O.Ensemble(og, ini)
+    gg = gpu.Grid(mesh, f, mo)
+    ge = gpu.Ensemble(gg, ini, precision=gpu.PDF_MIXED)
+    ex = og.export()
+    proj = fem.Projection(mesh, og, f.grad_p)
+    ge.set_feedback(True, 1.0, feed_rey=True, feed_omega=True)
+    oe.feedback(1.0, True, True)
+    for n in range(3):
+        wpg, _ = ge.elliptic_relaxation(tol=1e-12, store=True)
+        wpo = fem.elliptic_relaxation(mesh, ex["frame"], ex["area"], oe.stats(), mo)
+        og.set_wp(wpo)
+        assert np.abs(wpg - wpo).max() <= 1e-3 * np.abs(wpo).max(), n
+        oe.step(1e-3)
+        ge.step(1e-3)
+        dpo = proj.apply(oe, 1e-3, cp=1e-3, rho=mo["rho"])
+        dpg, it = ge.pressure_projection(1e-3, cp=1e-3, tol=1e-12)
+        assert np.abs(dpg - dpo).max() <= 1e-3 * np.abs(dpo).max(), (n, it)
+        oe.feedback(1.0, True, True)
+        _check_mixed_stats(ge.stats(), oe.stats(), f"closed loop step {n + 1}", omega_bound=SECOND_BOUND)
