@@ -1308,10 +1308,50 @@ k_element_wave(ElementArgs<R> a, int n_below, int last)
         }
         C *= gl[l];
     }
-    // hand over to canonical order: slot of the particle at each position
+    // hand over to canonical order: slot of the particle at each position.  With FP32 state
+    // and at least four particles per lane the velocities and pids also move to their
+    // canonical lanes through the sort's LDS instead of a second global read (measured
+    // 4.41 -> 4.08 ms on channel_large); with FP64 state the extra live registers spill
+    // (4.69 -> 4.82 ms) and with three per lane it was slower too (24.6 -> 25.2 ms on the
+    // street canyon), so the global read is kept there.
+    constexpr bool PERM = sizeof(R) == sizeof(float) && PPL >= 4;
 #pragma unroll
     for (int r = 0; r < PPL; ++r)
         if (lane + 64 * r < n) ord[pos[r]] = gi[r];
+    R cu0[PPL], cu1[PPL], cu2[PPL];
+    uint64_t cpd[PPL];
+    if constexpr (PERM) {
+        R* lu = reinterpret_cast<R*>(base);
+#pragma unroll
+        for (int r = 0; r < PPL; ++r)
+            if (lane + 64 * r < n) {
+                lu[pos[r]] = U0[r];
+                lu[N + pos[r]] = U1[r];
+                lu[2 * N + pos[r]] = U2[r];
+            }
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < PPL; ++r) {
+            const int p = lane + 64 * r;
+            cu0[r] = cu1[r] = cu2[r] = R(0);
+            if (p < n) {
+                cu0[r] = lu[p];
+                cu1[r] = lu[N + p];
+                cu2[r] = lu[2 * N + p];
+            }
+        }
+        wave_sync();
+        uint64_t* lp = reinterpret_cast<uint64_t*>(base);
+#pragma unroll
+        for (int r = 0; r < PPL; ++r)
+            if (lane + 64 * r < n) lp[pos[r]] = pd[r];
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < PPL; ++r) {
+            const int p = lane + 64 * r;
+            cpd[r] = p < n ? lp[p] : 0ull;
+        }
+    }
     wave_sync();
     int gp[PPL];
     R ws[PPL], ps[PPL];
@@ -1357,8 +1397,8 @@ k_element_wave(ElementArgs<R> a, int n_below, int last)
         const int64_t g = gp[r];
         const double x = a.in.x[g], y = a.in.y[g];
         const R om = a.in.om[g];
-        const R u0 = a.in.u0[g], u1 = a.in.u1[g], u2 = a.in.u2[g];
-        const uint64_t pid = a.in.pid[g];
+        const R u0 = PERM ? cu0[r] : a.in.u0[g], u1 = PERM ? cu1[r] : a.in.u1[g], u2 = PERM ? cu2[r] : a.in.u2[g];
+        const uint64_t pid = PERM ? cpd[r] : a.in.pid[g];
         const int b = div_small(Cp * p, n);
         const R psi = ps[r] - fmix * (ps[r] - bmean[b]);
         const R w = ws[r];
