@@ -89,7 +89,7 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
                 const ElemGeo* Gu = a.geo + eu;
                 double na, nb, nc;
                 area_coords(Gu, x0, y0, na, nb, nc);
-                const double ia = 1.0 / Gu->area;
+                const double ia = Gu->inv_area;
                 // statistics as element averages of the nodal values (second estimator of
                 // Sec. 3.3) or P1 interpolation (Eq. 37)
                 const bool avg = P.estimator == 1;
@@ -148,15 +148,16 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
     M::normal2(wA.w0, wA.w1, z0, z1);
     M::normal2(wA.w2, wA.w3, z2, z3);
     M::normal2(wB.w0, wB.w1, z4, z5);
-    const R sdt = M::sqrt_(dt);
+    // FP64: the host's correctly rounded values (the same as computing them here)
+    const R sdt = sizeof(R) == sizeof(double) ? (R)P.sdt : M::sqrt_(dt);
     const R dWx = sdt * z0, dWy = sdt * z1;
     const R dWp0 = sdt * z2, dWp1 = sdt * z3, dWp2 = sdt * z4, dWo = sdt * z5;
-    const R s2nu = M::sqrt_(R(2) * nu);
+    const R s2nu = sizeof(R) == sizeof(double) ? (R)P.s2nu : M::sqrt_(R(2) * nu);
     const R sc0 = M::sqrt_(c0eps);
 
     // velocity, Eq. (27)
     const R d0 = u0 - f[NF_MU], d1 = u1 - f[NF_MU + 1], d2 = u2 - f[NF_MU + 2];
-    const R irho = R(1) / rho;
+    const R irho = sizeof(R) == sizeof(double) ? (R)P.irho : R(1) / rho;
     const R dr0 = -f[NF_GP] * irho + R(2) * nu * f[NF_LAP] + G11 * d0 + G12 * d1 + G13 * d2;
     const R dr1 = -f[NF_GP + 1] * irho + R(2) * nu * f[NF_LAP + 1] + G21 * d0 + G22 * d1 + G23 * d2;
     const R dr2 = R(2) * nu * f[NF_LAP + 2] + G31 * d0 + G32 * d1 + G33 * d2;

@@ -245,6 +245,7 @@ pdf_status set_dt(pdf_ens_s* E, const double* dt, hipStream_t s)
     for (int p = 0; p < E->n_problems; ++p)
         if (E->h_prm[p].dt != dt[p]) {
             E->h_prm[p].dt = dt[p];
+            E->h_prm[p].sdt = std::sqrt(dt[p]);
             changed = true;
         }
     if (changed)
@@ -1195,6 +1196,9 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
             ProbParams P{};
             P.m = g->model;
             P.dt = 0.0;
+            P.sdt = 0.0;
+            P.s2nu = std::sqrt(2.0 * P.m.nu);
+            P.irho = 1.0 / P.m.rho;
             P.period = g->period;
             P.src_x = d.src_x;
             P.src_y = d.src_y;

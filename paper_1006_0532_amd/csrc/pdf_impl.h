@@ -96,6 +96,7 @@ struct ProbParams {
     int64_t noff, nn;              // node range
     int64_t soff;                  // first set-up slot
     uint64_t next_pid;             // next particle id of the problem
+    double sdt, s2nu, irho;        // sqrt(dt), sqrt(2 nu), 1 / rho (kept with dt and m)
 };
 
 }  // namespace pdfgpu
