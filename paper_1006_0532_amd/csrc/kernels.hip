@@ -1226,7 +1226,12 @@ k_element_wave(ElementArgs<R> a, int n_below, int last)
             C *= gl[0];
             continue;
         }
-        // later levels: rank inside the groups the previous level formed
+        // later levels: rank inside the groups the previous level formed (group t holds the
+        // positions ceil(t n / C) .. ceil((t + 1) n / C) - 1); the groups' first positions in
+        // a table, in the slot-order LDS that is free until the hand-over
+        int* gb = ord;
+        for (int t = lane; t < (int)C; t += 64) gb[t] = div_small(t * n + (int)C - 1, (int)C);
+        wave_sync();
         uint64_t mk[PPL];
         int lo[PPL], hi[PPL];
         uint64_t kmin = ~0ull, kmax = 0ull;
@@ -1234,8 +1239,8 @@ k_element_wave(ElementArgs<R> a, int n_below, int last)
         for (int r = 0; r < PPL; ++r) {
             mk[r] = order_bits(l == 1 ? U1[r] : U2[r]);
             const int t = div_small((int)C * pos[r], n);
-            lo[r] = div_small(t * n + (int)C - 1, (int)C);
-            hi[r] = div_small((t + 1) * n + (int)C - 1, (int)C);
+            lo[r] = gb[t];
+            hi[r] = t + 1 < (int)C ? gb[t + 1] : n;
             if (lane + 64 * r < n) {
                 kmin = mk[r] < kmin ? mk[r] : kmin;
                 kmax = mk[r] > kmax ? mk[r] : kmax;
