@@ -32,3 +32,13 @@ def edge_distance(frame, e, x, y):
         L = math.hypot(ex, ey)
         d = min(d, abs((x - a[0]) * ey - (y - a[1]) * ex) / L)
     return d
+
+
+def shift_periodic(mesh, dx):
+    """The same periodic mesh with every node moved by -dx in x (mod the period): an input
+    transform that puts a chosen column of nodes on the seam x = 0."""
+    L = mesh.period_x
+    xy = mesh.xy.copy()
+    xy[:, 0] = np.mod(xy[:, 0] - dx, L)
+    xy[xy[:, 0] >= L, 0] = 0.0
+    return W.Mesh(xy, mesh.tri, mesh.edge_kind, L, dict(mesh.meta))
