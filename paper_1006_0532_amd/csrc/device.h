@@ -1,5 +1,5 @@
 // Device building blocks of libpdfgpu: counter-based random numbers, P1 geometry,
-// wavefront collectives.  Included by the kernel translation unit only.
+// wavefront collectives.  Included by the translation units that hold kernels.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -226,6 +226,27 @@ __device__ __forceinline__ void area_coords(const ElemGeo* __restrict__ G, doubl
     na = 0.5 * fma(xc - xb, y - yb, -((yc - yb) * (x - xb)));
     nc = 0.5 * fma(x - xb, ya - yb, -((y - yb) * (xa - xb)));
     nb = G->area - na - nc;
+}
+
+// Eq. (26) ingredients of node n: l = sqrt of the average area of the elements around the
+// node (inf without elements), z = |(<U1>, <U2>, <U3>, <omega>, <psi>)| where the node has
+// statistics (W > 0), else 0
+__device__ __forceinline__ void cfl_node(const ElemGeo* __restrict__ geo, const int64_t* __restrict__ n2e_ptr,
+                                         const int32_t* __restrict__ n2e, const double* __restrict__ stats, int64_t n,
+                                         double& l, double& z)
+{
+    const int64_t j0 = n2e_ptr[n], j1 = n2e_ptr[n + 1];
+    if (j1 > j0) {
+        double a = 0.0;
+        for (int64_t j = j0; j < j1; ++j) a += geo[n2e[j] / 3].area;
+        l = sqrt(a / (double)(j1 - j0));
+    }
+    const double* o = stats + n * NSTAT;
+    if (o[0] > 0.0) {
+        double s = 0.0;
+        for (int q = 1; q <= 5; ++q) s += o[q] * o[q];
+        z = sqrt(s);
+    }
 }
 
 // ------------------------------------------------------------------------------------

@@ -1719,19 +1719,26 @@ __global__ void __launch_bounds__(256) k_ctl_apply(ControlArgs<R> a)
     }
 }
 
-// slots and live count after control, the clone total, and every problem's next pid
+// slots and live count after control, the clone total, and every problem's next pid.
+// Clones are written in the order of their offsets, so when the capacity cut them short
+// the ones that exist are the first room = cap - slots of that order: a prefix of every
+// problem's range, whose pids stay contiguous.
 __global__ void k_ctl_finish(int64_t* __restrict__ meta, const int32_t* __restrict__ off, int64_t ne,
                              const unsigned long long* __restrict__ rep, int64_t cap, ProbParams* __restrict__ prm,
                              int32_t n_problems)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const int64_t total = off[ne];
-    int64_t slots = meta[0] + total;
-    meta[0] = slots > cap ? cap : slots;
-    meta[1] = meta[1] - (int64_t)rep[0] + total;
-    meta[2] = total;
-    for (int p = 0; p < n_problems; ++p)
-        prm[p].next_pid += (uint64_t)(off[prm[p].eoff + prm[p].ne] - off[prm[p].eoff]);
+    const int64_t room = cap - meta[0] > 0 ? cap - meta[0] : 0;
+    const int64_t made = total < room ? total : room;
+    meta[0] += made;
+    meta[1] = meta[1] - (int64_t)rep[0] + made;
+    meta[2] = made;
+    for (int p = 0; p < n_problems; ++p) {
+        const int64_t lo = off[prm[p].eoff], hi = off[prm[p].eoff + prm[p].ne];
+        const int64_t fit = made - lo < 0 ? 0 : (made - lo > hi - lo ? hi - lo : made - lo);
+        prm[p].next_pid += (uint64_t)fit;
+    }
 }
 
 // Particle redistribution (App. B), applied in two passes so that a slot that serves as a
@@ -1934,20 +1941,7 @@ __global__ void __launch_bounds__(256) k_cfl(const ElemGeo* __restrict__ geo, co
 {
     const int64_t n = n0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
     double l = __builtin_inf(), z = 0.0;
-    if (n < n0 + nn) {
-        const int64_t j0 = n2e_ptr[n], j1 = n2e_ptr[n + 1];
-        if (j1 > j0) {
-            double a = 0.0;
-            for (int64_t j = j0; j < j1; ++j) a += geo[n2e[j] / 3].area;
-            l = sqrt(a / (double)(j1 - j0));
-        }
-        const double* o = stats + n * NSTAT;
-        if (o[0] > 0.0) {
-            double s = 0.0;
-            for (int q = 1; q <= 5; ++q) s += o[q] * o[q];
-            z = sqrt(s);
-        }
-    }
+    if (n < n0 + nn) cfl_node(geo, n2e_ptr, n2e, stats, n, l, z);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         l = fmin(l, __shfl_xor(l, o));

@@ -235,25 +235,36 @@ class Ensemble:
     def stats_device(self, ptr: int, problem: int = 0):
         _check(load().pdf_stats(self.h, int(problem), C.c_void_p(ptr), 1, C.c_void_p(self.stream)))
 
-    def control(self, n_min: int, n_max: int) -> dict:
+    # check=False: a sticky device error does not raise; its status is kept in
+    # self.last_status and the call's outputs (filled before the error is reported) are
+    # returned, so that the state after the error can be inspected
+    def _status(self, st: int, check: bool):
+        self.last_status = int(st)
+        if check:
+            _check(st)
+        elif st not in (0, -5, -6, -7):
+            _check(st)
+
+    def control(self, n_min: int, n_max: int, check: bool = True) -> dict:
         r = ControlReport()
-        _check(load().pdf_control(self.h, int(n_min), int(n_max), C.byref(r), C.c_void_p(self.stream)))
+        self._status(load().pdf_control(self.h, int(n_min), int(n_max), C.byref(r), C.c_void_p(self.stream)),
+                     check)
         return {n: getattr(r, n) for n, _ in ControlReport._fields_}
 
-    def count(self, problem: int = -1) -> int:
+    def count(self, problem: int = -1, check: bool = True) -> int:
         v = C.c_int64()
-        _check(load().pdf_count(self.h, int(problem), C.byref(v)))
+        self._status(load().pdf_count(self.h, int(problem), C.byref(v)), check)
         return int(v.value)
 
-    def export(self, sort_by_pid: bool = True, problem: int = 0) -> dict:
-        n = self.count(problem)
+    def export(self, sort_by_pid: bool = True, problem: int = 0, check: bool = True) -> dict:
+        n = self.count(problem, check)
         o = dict(x=np.empty(n), y=np.empty(n), u=np.empty((n, 3)), om=np.empty(n), psi=np.empty(n),
                  w=np.empty(n), pid=np.empty(n, np.uint64), elem=np.empty(n, np.int32))
         got = C.c_int64()
-        _check(load().pdf_particles_export(self.h, int(problem), n, *[_ptr(o[k], C.c_double) for k in
-                                                                      ("x", "y", "u", "om", "psi", "w")],
-                                           _ptr(o["pid"], C.c_uint64), _ptr(o["elem"], C.c_int32),
-                                           C.byref(got), C.c_void_p(self.stream)))
+        self._status(load().pdf_particles_export(self.h, int(problem), n, *[_ptr(o[k], C.c_double) for k in
+                                                                            ("x", "y", "u", "om", "psi", "w")],
+                                                 _ptr(o["pid"], C.c_uint64), _ptr(o["elem"], C.c_int32),
+                                                 C.byref(got), C.c_void_p(self.stream)), check)
         assert got.value == n
         if sort_by_pid:
             order = np.argsort(o["pid"], kind="stable")

@@ -287,6 +287,61 @@ def test_error_paths(gpu):
     assert ex.value.status == -4
 
 
+def test_capacity_error_keeps_the_state_consistent(gpu):
+    """Number control asks for more clones than the capacity holds: PDF_E_CAPACITY, the
+    clones that fit are written (a prefix of the clone order, contiguous new pids), none
+    past the capacity, the donors of the missing ones keep their weight, so the total
+    weight and the weighted sums are unchanged, and the live count is the slots used."""
+    _say("test_capacity_error_keeps_the_state_consistent")
+    mesh, f, mo, ini = W.channel_small(nx=8, ny=10)
+    n0 = mesh.n_elems * ini["ppe"]
+    cap = n0 + 800
+    e = gpu.Ensemble(gpu.Grid(mesh, f, mo), ini, capacity=cap)
+    e.step(1e-3)
+    before = e.export()
+    rep = e.control(60, 80, check=False)
+    assert e.last_status == -5
+    assert rep["cloned"] == 800 and rep["live"] == cap, rep
+    assert e.count(check=False) == cap and e.last_status == -5
+    after = e.export(check=False)
+    assert e.last_status == -5
+    assert len(after["pid"]) == cap
+    assert len(np.unique(after["pid"])) == cap
+    new = after["pid"] >= n0
+    assert new.sum() == 800 and np.array_equal(np.sort(after["pid"][new]), np.arange(n0, n0 + 800))
+    assert np.array_equal(after["pid"][~new], before["pid"])
+    for k in ("w",):
+        assert abs(after[k].sum() - before[k].sum()) <= 1e-12 * before[k].sum()
+    wu = lambda st: (st["w"][:, None] * st["u"]).sum(0)
+    assert np.abs(wu(after) - wu(before)).max() <= 1e-12 * np.abs(wu(before)).max()
+    # every clone is a half-weight copy of a donor that now has half its weight
+    halved = after["w"][~new] < before["w"]
+    assert halved.sum() == 800 and np.all(after["w"][new] == 0.5)
+    with pytest.raises(gpu.PdfError) as ex:
+        e.sync()
+    assert ex.value.status == -5
+
+
+def test_nonfinite_inputs_are_rejected(gpu):
+    """A NaN nodal field is refused by pdf_grid_create, and a NaN particle velocity by
+    pdf_particles_import, both with PDF_E_NONFINITE."""
+    _say("test_nonfinite_inputs_are_rejected")
+    mesh, f, mo, ini = W.channel_small(nx=8, ny=10)
+    for name in ("mean_u", "mean_omega", "grad_p", "wp", "rey"):
+        bad = W.Fields(*[a.copy() for a in f.as_tuple()])
+        arr = getattr(bad, name)
+        arr.reshape(-1)[7] = np.nan
+        with pytest.raises(gpu.PdfError) as ex:
+            gpu.Grid(mesh, bad, mo)
+        assert ex.value.status == -7, name
+    e = gpu.Ensemble(gpu.Grid(mesh, f, mo), ini)
+    st = e.export()
+    st["u"][3, 1] = np.inf
+    with pytest.raises(gpu.PdfError) as ex:
+        e.import_state(st, step=0, next_pid=len(st["x"]))
+    assert ex.value.status == -7
+
+
 def test_elements_above_the_wavefront_limit(gpu):
     """An ensemble seeded with 40 per element holds at most 64 per wavefront; importing
     600 per element sends every element to the workgroup kernel's on-chip path."""
@@ -379,6 +434,35 @@ def test_cavity_small_parity(gpu):
     c = ge.counters()
     assert c["wall_a"] > 0 and c["reflections"] > 0 and c["source_hits"] > 0
     assert c == oe.counters()
+
+
+@pytest.mark.parametrize("U", [(-1.0, 1.0), (1.0, 1.0)])
+def test_concave_fallback_parity(gpu, U):
+    """Concave-boundary fall-back of Sec. 3.6 (Fig. 2): a small street canyon with one
+    re-entrant corner on the periodic seam, a frozen velocity that carries particles
+    round a corner every step and long steps; the fall-back fires dozens of times a step
+    (across the seam for U = (-1, 1)) and the GPU agrees with the oracle particle by
+    particle, in its counters and in the statistics.  The fields keep C0 eps > 0: with it
+    clamped to zero, every particle that left a no-slip wall at U = 0 would take the same
+    deterministic velocity up to the last bit, and the velocity sorts of the binning would
+    order such near-ties by rounding, which the two sides need not share."""
+    _say(f"test_concave_fallback_parity U={U}")
+    from tests.test_oracle_fallback import canyon_on_seam
+    mesh = canyon_on_seam()
+    f = W.uniform_fields(mesh, mean_u=(U[0], U[1], 0.0), mean_omega=1.0)
+    mo = W.model_constants(nu=1.0e-4)
+    ini = W.init_desc(ppe=300, u_sigma=0.02, src_x=0.5, src_y=0.5, src_r=0.1)
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    excl = set()
+    for n in range(4):
+        oe.step(0.05)
+        ge.step(0.05)
+        rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+    compare_stats(ge.stats(), oe.stats(), _skip_nodes(mesh, excl))
+    c = ge.counters()
+    assert c == oe.counters()
+    assert c["fallbacks"] > 50 and c["wall_a"] > 0, c
 
 
 @pytest.mark.parametrize("feed_rey", [False, True])
