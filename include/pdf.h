@@ -334,6 +334,18 @@ pdf_status pdf_pressure_projection(pdf_ens ens, double dt, double cp, double tol
  * particles do not enter the maximum; 0 when no node has a positive norm.  Synchronises. */
 pdf_status pdf_cfl_dt(pdf_ens ens, int32_t problem, double cfl, double* dt_out, void* hip_stream);
 
+/* pdf_cfl_dt without any allocation, for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc).  Writes the same
+ * time step as pdf_cfl_dt (bit for bit) into dt_out, one double in device memory owned by the
+ * caller, as work enqueued on hip_stream: no synchronisation, no host copy.  The statistics
+ * it reads must be complete in hip_stream's order (pass the stream of the pdf_step calls).
+ * Its partial results live in a fixed array of the library, 1 MiB on every device it runs on
+ * (looked up at pdf_particles_init), held until the process ends: calls that overlap on one
+ * device race for it and must be ordered by the caller (one stream, or events).
+ * Errors: PDF_E_INVAL, PDF_E_CAPACITY (the problem has more than 2^24 nodes), PDF_E_STATE
+ * (the array of the device could not be set up), PDF_E_HIP. */
+pdf_status pdf_cfl_dt_noalloc(pdf_ens ens, int32_t problem, double cfl, double* dt_out, void* hip_stream);
+
 /* Launch options of an ensemble; none changes any result.
  *  use_graph  1: pdf_step replays every two steps from a captured HIP graph on a
  *             stream of the ensemble (ordered after and before hip_stream by events),

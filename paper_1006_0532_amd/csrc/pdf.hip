@@ -21,6 +21,7 @@ using namespace pdfgpu;
 
 namespace pdfgpu {
 pdf_status build_grid(pdf_grid_s& g, const pdf_mesh_desc& m, const pdf_fields_desc& f);
+double* noalloc_scratch(int device);
 
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -1176,6 +1177,9 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
     }
     pdf_grid_s* g0 = grids[0];
     HIP_TRY(hipSetDevice(g0->device));
+    // device address of the fixed scratch of pdf_cfl_dt_noalloc, looked up once per device
+    // (a failure is reported by that call, not here)
+    (void)noalloc_scratch(g0->device);
     hipStream_t s = as_stream(hip_stream);
     pdf_ens_s* E = new pdf_ens_s();
     E->grid = g0;

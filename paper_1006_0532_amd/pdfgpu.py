@@ -27,7 +27,7 @@ STATUS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "HIP", -4: "MESH", -5: "CAPACIT
 # every symbol include/pdf.h declares
 EXPORTS = ["pdf_grid_create", "pdf_grid_destroy", "pdf_particles_init", "pdf_ens_destroy", "pdf_step",
            "pdf_stats", "pdf_control", "pdf_count", "pdf_particles_export", "pdf_particles_import",
-           "pdf_counters", "pdf_timing", "pdf_set_feedback", "pdf_cfl_dt", "pdf_redistribute", "pdf_elliptic_relaxation",
+           "pdf_counters", "pdf_timing", "pdf_set_feedback", "pdf_cfl_dt", "pdf_cfl_dt_noalloc", "pdf_redistribute", "pdf_elliptic_relaxation",
            "pdf_pressure_projection", "pdf_get_options", "pdf_set_options", "pdf_autotune",
            "pdf_sync",
            "pdf_last_error"]
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
         "pdf_timing": [vp, C.c_int32, dp, i64p],
         "pdf_set_feedback": [vp, C.c_int32, C.c_double, C.c_int32, vp],
         "pdf_cfl_dt": [vp, C.c_int32, C.c_double, dp, vp],
+        "pdf_cfl_dt_noalloc": [vp, C.c_int32, C.c_double, vp, vp],
         "pdf_redistribute": [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64), vp],
         "pdf_elliptic_relaxation": [vp, C.POINTER(EllipticModel), C.c_double, C.c_int32, C.c_int32, vp, C.c_int32,
                                     C.POINTER(C.c_int32), vp],
@@ -302,6 +303,11 @@ class Ensemble:
         v = C.c_double()
         _check(load().pdf_cfl_dt(self.h, int(problem), float(cfl), C.byref(v), C.c_void_p(self.stream)))
         return float(v.value)
+
+    def cfl_dt_noalloc(self, dt_out_ptr: int, cfl: float = 0.7, problem: int = 0):
+        """Eq. (26) into one double of device memory at dt_out_ptr (enqueued, no sync)."""
+        _check(load().pdf_cfl_dt_noalloc(self.h, int(problem), float(cfl), C.c_void_p(dt_out_ptr),
+                                         C.c_void_p(self.stream)))
 
     def redistribute(self, n_min: int, problem: int = -1) -> int:
         """Particle redistribution of App. B; returns the number of moves."""
