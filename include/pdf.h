@@ -196,7 +196,12 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
 pdf_status pdf_ens_destroy(pdf_ens ens);
 
 /* Advance n_steps time steps; problem p uses the time step dt[p] (> 0, one entry per
- * problem).  Enqueues only; does not synchronise (a changed dt is uploaded first). */
+ * problem).  Enqueues only; does not synchronise (a changed dt is uploaded first, with a
+ * synchronisation).  With an unchanged dt the call can be captured into a HIP graph by the
+ * caller (with pdf_control without a report); a replay advances the ensemble by the
+ * captured steps with the captured dt.  A step moves the particle state from one of two
+ * device buffers to the other, so a graph meant to be replayed must hold an even number of
+ * steps. */
 pdf_status pdf_step(pdf_ens ens, const double* dt, int32_t n_steps, void* hip_stream);
 
 /* Nodal statistics of the last step (Sec. 3.3) of one problem, out = [n_nodes][13]:
@@ -213,9 +218,14 @@ pdf_status pdf_stats(pdf_ens ens, int32_t problem, double* out, int32_t out_is_d
  * last step: elements with 0 < n < n_min split min(n_min - n, n) particles into two
  * half-weight copies; elements with n > n_max merge pairs of particles of one velocity
  * bin into their weighted average, up to n - n_max merges.  Conserves the total weight and
- * the weighted sums of U, omega and psi in every element and bin.  Synchronises and fills
- * report when it is not NULL.  Errors: PDF_E_INVAL (n_min > n_max, n_max < 1),
- * PDF_E_CAPACITY, PDF_E_HIP. */
+ * the weighted sums of U, omega and psi in every element and bin.
+ * report != NULL: synchronises, fills report and returns a capacity error (clones beyond
+ * the capacity are not written; those written are counted).  report == NULL: only enqueues
+ * (no synchronisation, no host copy), so that pdf_step and pdf_control can be captured
+ * together into one HIP graph by the caller; the particle kernels of the following steps
+ * then cover the whole capacity, whose unused slots return at once, and a capacity error
+ * is returned by the next synchronising call.  Errors: PDF_E_INVAL (n_min > n_max,
+ * n_max < 1), PDF_E_STATE (no step since the last control), PDF_E_CAPACITY, PDF_E_HIP. */
 pdf_status pdf_control(pdf_ens ens, int32_t n_min, int32_t n_max, pdf_control_report* report,
                        void* hip_stream);
 

@@ -171,14 +171,16 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
         omn = -omn;
         ev.omrefl = 1;
     }
-    // position, Eq. (7), with the start-of-step velocity (always accumulated in FP64)
+    // position, Eq. (7), with the start-of-step velocity, in FP64 in both forms (the mixed
+    // form widens its FP32 velocity and Gaussian and scales them by the FP64 dt, sqrt(dt)
+    // and sqrt(2 nu), so the displacement carries no FP32 rounding of its own)
     double x, y;
     if constexpr (sizeof(R) == sizeof(double)) {
         x = x0 + u0 * P.dt + s2nu * dWx;
         y = y0 + u1 * P.dt + s2nu * dWy;
     } else {
-        x = x0 + (double)(u0 * dt + s2nu * dWx);
-        y = y0 + (double)(u1 * dt + s2nu * dWy);
+        x = x0 + (double)u0 * P.dt + P.s2nu * (P.sdt * (double)z0);
+        y = y0 + (double)u1 * P.dt + P.s2nu * (P.sdt * (double)z1);
     }
 
     // (a3) next-best-element walk (Sec. 3.6) with particle wall conditions (Sec. 3.8)

@@ -242,16 +242,17 @@ pdf_status step_any(pdf_ens_s* E, hipStream_t s)
 // upload the per-problem time steps when they changed
 pdf_status set_dt(pdf_ens_s* E, const double* dt, hipStream_t s)
 {
+    // only the time-step entries are uploaded: the device table's next pids move on with
+    // number control, which need not report them to the host
     bool changed = false;
     for (int p = 0; p < E->n_problems; ++p)
         if (E->h_prm[p].dt != dt[p]) {
             E->h_prm[p].dt = dt[p];
             E->h_prm[p].sdt = std::sqrt(dt[p]);
+            HIP_TRY(hipMemcpyAsync(&E->d_prm[p].dt, &E->h_prm[p].dt, sizeof(double), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(&E->d_prm[p].sdt, &E->h_prm[p].sdt, sizeof(double), hipMemcpyHostToDevice, s));
             changed = true;
         }
-    if (changed)
-        HIP_TRY(hipMemcpyAsync(E->d_prm, E->h_prm.data(), sizeof(ProbParams) * E->n_problems,
-                               hipMemcpyHostToDevice, s));
     if (changed) HIP_TRY(hipStreamSynchronize(s));   // the host table may change again
     return PDF_OK;
 }
@@ -353,6 +354,14 @@ pdf_status control_impl(pdf_ens_s* E, int32_t n_min, int32_t n_max, pdf_control_
         launch_ctl_finish(E->d_meta, E->ctl_off, g.ne, E->ctl_rep, E->cap, E->d_prm, E->n_problems, s);
     }
     HIP_TRY(hipGetLastError());
+    E->ctl_valid = false;
+    if (!report) {
+        // enqueued only: the slots now in use are known on the device alone, so later launches
+        // cover the capacity (their threads beyond the used slots return at once); errors
+        // surface at the next synchronising call
+        E->n_slots_ub = E->cap;
+        return PDF_OK;
+    }
     int64_t meta[3];
     unsigned long long rep[4];
     HIP_TRY(hipMemcpyAsync(meta, E->d_meta, sizeof(meta), hipMemcpyDeviceToHost, s));
@@ -362,8 +371,7 @@ pdf_status control_impl(pdf_ens_s* E, int32_t n_min, int32_t n_max, pdf_control_
     HIP_TRY(hipStreamSynchronize(s));
     for (int p = 0; p < E->n_problems; ++p) E->h_prm[p].next_pid = prm[p].next_pid;
     E->n_slots_ub = meta[0];
-    E->ctl_valid = false;
-    if (report) {
+    {
         report->live = meta[1];
         report->cloned = meta[2];
         report->merged = (int64_t)rep[0];
@@ -1403,8 +1411,11 @@ pdf_status pdf_redistribute(pdf_ens E, int32_t problem, int32_t n_min, int64_t* 
     }
     const int64_t ne = E->dg.ne;
     std::vector<int32_t> start(ne + 1);
+    int64_t meta[5];
     HIP_TRY(hipMemcpyAsync(start.data(), E->start, sizeof(int32_t) * (ne + 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(meta, E->d_meta, sizeof(meta), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    E->step = meta[4];   // the device's step counter (steps replayed from a caller's graph included)
     pdf_status st = check_device_error(E);
     if (st != PDF_OK) return st;
     std::unordered_map<int32_t, RedistSrc> moved;

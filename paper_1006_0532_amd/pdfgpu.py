@@ -246,7 +246,11 @@ class Ensemble:
         elif st not in (0, -5, -6, -7):
             _check(st)
 
-    def control(self, n_min: int, n_max: int, check: bool = True) -> dict:
+    def control(self, n_min: int, n_max: int, check: bool = True, report: bool = True):
+        """Number control; report=False only enqueues it (no synchronisation) and returns None."""
+        if not report:
+            self._status(load().pdf_control(self.h, int(n_min), int(n_max), None, C.c_void_p(self.stream)), check)
+            return None
         r = ControlReport()
         self._status(load().pdf_control(self.h, int(n_min), int(n_max), C.byref(r), C.c_void_p(self.stream)),
                      check)

@@ -62,13 +62,14 @@ def field_errors(s, ref):
     return out, int((~ok).sum())
 
 
-def _check_mixed_stats(sg, so, label, omega_bound=MEAN_BOUND):
+def _check_mixed_stats(sg, so, label, check_omega=True):
     err, nan_nodes = field_errors(sg, so)
     _say(f"  {label}: W-weighted relative L2 per field: " + ", ".join(f"{k} {v:.2e}" for k, v in err.items()))
     assert nan_nodes == int(np.isnan(so).any(axis=1).sum())
     for k in ("W", "U"):
         assert err[k] <= MEAN_BOUND, (k, err)
-    assert err["omega"] <= omega_bound, ("omega", err)
+    if check_omega:
+        assert err["omega"] <= MEAN_BOUND, ("omega", err)
     for k in ("psi", "R", "psi_var"):
         assert err[k] <= SECOND_BOUND, (k, err)
     return err
@@ -376,12 +377,7 @@ def test_large_cavity_mixed_against_fp64(gpu, name):
     b.step(dt, 10)
     sb = b.stats()
     assert b.count() == n0
-    # at this size a single particle of 10^8 next to the street-level wall takes a different
-    # discrete tracking decision in the mixed form (positions differ from the FP64 run by
-    # about 1e-12): its frequency, drawn again at the wall, differs by O(1) and moves the
-    # W-weighted relative L2 of <omega> to about 1.3e-5; the per-particle differences of all
-    # others stay below 1e-6 (99.999 % quantile), so <omega> is held to the 1e-4 bound here
-    _check_mixed_stats(sb, sa, f"{name}, 10 steps", omega_bound=SECOND_BOUND)
+    err = _check_mixed_stats(sb, sa, f"{name}, 10 steps", check_omega=False)
     assert b.counters()["wall_a"] > 0 and ca["wall_a"] > 0     # the canyon's walls are hit
     lo, hi = ini["ppe"] - 2, ini["ppe"] + 2          # tight bounds: both splits and merges occur
     for n in range(2):
@@ -392,6 +388,14 @@ def test_large_cavity_mixed_against_fp64(gpu, name):
         assert r["cloned"] > 0 and r["merged"] > 0
     b.close()
     gg.close()
+    if name == "cavity_large" and err["omega"] > MEAN_BOUND:
+        # a known miss of the 1e-5 bound on means: one particle of 10^8 next to the street-level
+        # wall takes the other side of the Eq. (53) test in the mixed run (its FP32 velocity
+        # moved it by about 1e-12 from the FP64 run's position), so its frequency is drawn again
+        # at the wall and differs by O(1); that alone gives <omega> a W-weighted relative L2 of
+        # about 1.3e-5, while the other particles' frequencies agree to 1e-6
+        pytest.xfail(f"<omega> of the mixed form on cavity_large: {err['omega']:.2e} > {MEAN_BOUND:.0e}")
+    assert err["omega"] <= MEAN_BOUND, ("omega", err)
 
 
 def test_mixed_closed_loop(gpu):
@@ -424,4 +428,61 @@ def test_mixed_closed_loop(gpu):
         dpg, it = ge.pressure_projection(1e-3, cp=1e-3, tol=1e-12)
         assert np.abs(dpg - dpo).max() <= 1e-3 * np.abs(dpo).max(), (n, it)
         oe.feedback(1.0, True, True)
-        _check_mixed_stats(ge.stats(), oe.stats(), f"closed loop step {n + 1}", omega_bound=SECOND_BOUND)
+        _check_mixed_stats(ge.stats(), oe.stats(), f"closed loop step {n + 1}")
+
+
+def test_step_and_control_captured_in_one_graph(gpu):
+    """pdf_control without a report only enqueues, so a caller can capture steps and their
+    number control into one HIP graph (two steps: a step moves the state between two
+    buffers, so an even number of them returns it to the buffer the graph starts from):
+    four replays (with synchronisations and host work between them) give bitwise the state
+    and statistics of the same calls made eagerly, and of eager calls whose control reports
+    (and synchronises)."""
+    import ctypes as C
+    _say("test_step_and_control_captured_in_one_graph")
+    hip = C.CDLL("libamdhip64.so.7")   # by soname: the HIP runtime already loaded, which libpdfgpu uses
+    mesh = W.channel_mesh(20, 24, stretch=1.1 ** 8, seed=21)
+    f = W.channel_fields(mesh)
+    mo = W.model_constants()
+    ini = W.init_desc(ppe=40, bins=(4, 2, 2), src_x=3.0, src_r=0.4)
+    gg = gpu.Grid(mesh, f, mo)
+    stream = C.c_void_p()
+    assert hip.hipStreamCreate(C.byref(stream)) == 0
+    dt, ctl = 2e-3, (38, 42)
+    eager = gpu.Ensemble(gg, ini, stream=stream.value)
+    synced = gpu.Ensemble(gg, ini, stream=stream.value)
+    graphed = gpu.Ensemble(gg, ini, stream=stream.value)
+    for e in (eager, synced, graphed):
+        e.step(dt)
+    eager.control(*ctl, report=False)
+    synced.control(*ctl)
+    graphed.control(*ctl, report=False)
+    graph, exe = C.c_void_p(), C.c_void_p()
+    assert hip.hipStreamBeginCapture(stream, 1) == 0       # thread-local capture mode
+    for _ in range(2):
+        graphed.step(dt)
+        graphed.control(*ctl, report=False)
+    assert hip.hipStreamEndCapture(stream, C.byref(graph)) == 0
+    assert hip.hipGraphInstantiate(C.byref(exe), graph, None, None, C.c_size_t(0)) == 0
+    for n in range(4):
+        assert hip.hipGraphLaunch(exe, stream) == 0
+        for _ in range(2):
+            eager.step(dt)
+            eager.control(*ctl, report=False)
+            synced.step(dt)
+            rep = synced.control(*ctl)
+            assert rep["cloned"] > 0 and rep["merged"] > 0
+        assert hip.hipStreamSynchronize(stream) == 0
+        a, b, c = graphed.export(), eager.export(), synced.export()
+        for k in a:
+            assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), (n, k)
+        sa, sb = graphed.stats(), eager.stats()
+        assert np.array_equal(sa, sb, equal_nan=True) and np.array_equal(sa, synced.stats(), equal_nan=True), n
+        assert graphed.counters() == eager.counters() == synced.counters()
+        assert graphed.count() == synced.count()
+    hip.hipGraphExecDestroy(exe)
+    hip.hipGraphDestroy(graph)
+    for e in (eager, synced, graphed):
+        e.close()
+    gg.close()
+    hip.hipStreamDestroy(stream)
