@@ -23,12 +23,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP64 vector issue of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one FP64 lane
-# operation per lane and cycle; the 78.6 TFLOP/s figure counts a fused multiply-add twice)
+# VALU issue of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions per second
+# (a wavefront instruction holds its SIMD for 4 cycles; FP64 arithmetic issues at this rate)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# algorithmic VALU lane operations per particle of the particle loop (interpolation,
-# closure, 2 Philox blocks, 3 Box-Muller pairs, Eqs. 27, 19, 7, one tracking test)
-VALU_OPS_PER_PARTICLE = {"advance": 1000}
+FP64_PEAK_TFLOPS = 78.6
 
 # algorithmic HBM bytes per live particle (FP64 state): what each kernel must read and
 # write once
@@ -43,24 +41,44 @@ BYTES_PER_PARTICLE = {
 
 
 KERNEL_NAMES = {"advance": "k_advance", "element_pass": "k_element_wave", "scatter": "k_place"}
-COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_channel_large.txt")
+COUNTERS = os.path.join(ROOT, "profiles", "counters_channel_large.txt")
+COUNTERS_HUGE = os.path.join(ROOT, "profiles", "counters_cavity_huge_mixed.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1006_0532_amd", "csrc", "kernels.hip")
 
 
-def counter_traffic(kernel, default_workload):
-    """HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE) from the committed rocprofv3
-    counter summary of this workload, or None if the kernels changed since it was taken."""
-    if not default_workload or not os.path.exists(COUNTERS):
+def measured(kernel, name, default_workload, path=COUNTERS):
+    """A figure measured by rocprofv3 counters on this workload (the committed summary's
+    "measure <kernel> <name> <value>" lines), or None when the workload differs or the
+    kernels changed since the counters were taken."""
+    if not default_workload or not os.path.exists(path):
         return None
     sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
-    text = open(COUNTERS).read().splitlines()
+    text = open(path).read().splitlines()
     if f"kernels.hip sha256 prefix: {sha}" not in text:
         return None
     for line in text:
         f = line.split()
-        if len(f) == 3 and f[0] == "traffic_bytes_per_launch" and f[1] == KERNEL_NAMES.get(kernel):
-            return float(f[2])
+        if len(f) == 4 and f[0] == "measure" and f[1] == KERNEL_NAMES.get(kernel, kernel) and f[2] == name:
+            return float(f[3])
     return None
+
+
+def counter_traffic(kernel, default_workload, path=COUNTERS):
+    """HBM bytes per launch (32-, 64- and 128-byte read requests and 32- and 64-byte write
+    requests of the L2 to memory, counted by rocprofv3) of this workload, or None."""
+    rd = measured(kernel, "read_bytes_per_launch", default_workload, path)
+    wr = measured(kernel, "write_bytes_per_launch", default_workload, path)
+    return None if rd is None or wr is None else rd + wr
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def parse():
@@ -113,10 +131,50 @@ def cpu_baseline(args, dt, ctl):
         if done >= 2 and el >= args.cpu_seconds:
             break
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    one = cpu_baseline_one_thread(args, dt, ctl)
     return {"value": psteps / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"channel generator at {nx}x{ny} quads ({2 * nx * ny} triangles), "
                       f"{args.ppe} particles/element, {done} steps of dt={dt} with control "
-                      f"{list(ctl)}, {el:.1f} s"}
+                      f"{list(ctl)}, {el:.1f} s",
+            "one_thread": one}
+
+
+ONE_THREAD = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle as O
+from paper_1006_0532_amd import workloads as W
+nx, ny, ppe, dt, lo, hi, secs = int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4]), float(sys.argv[5]), \
+    int(sys.argv[6]), int(sys.argv[7]), float(sys.argv[8])
+m = W.channel_mesh(nx, ny)
+e = O.Ensemble(O.Grid(m, W.channel_fields(m), W.model_constants()), W.init_desc(ppe=ppe, bins=(4, 2, 2)))
+done, ps, t0 = 0, 0, time.perf_counter()
+while True:
+    n = e.count(); e.step(dt); e.control(lo, hi); ps += n; done += 1
+    el = time.perf_counter() - t0
+    if done >= 2 and el >= secs:
+        break
+print(json.dumps({"value": ps / el, "steps": done, "seconds": el}))
+"""
+
+
+def cpu_baseline_one_thread(args, dt, ctl):
+    """The oracle on one thread (a child process with OMP_NUM_THREADS=1) on a smaller
+    sample of the same generator."""
+    import subprocess
+    nx, ny = 50, 62
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", ONE_THREAD, ROOT, str(nx), str(ny), str(args.ppe), str(dt),
+                            str(ctl[0]), str(ctl[1]), str(max(2.0, args.cpu_seconds / 2))],
+                           env=env, capture_output=True, text=True, timeout=300)
+        d = json.loads(r.stdout.strip().splitlines()[-1])
+    except Exception as ex:   # reported, not fatal: the baseline is context
+        return {"error": str(ex)[:200]}
+    return {"value": d["value"], "unit": "particle-steps/s", "cores": 1,
+            "sample": f"channel generator at {nx}x{ny} quads ({2 * nx * ny} triangles), {args.ppe} "
+                      f"particles/element, {d['steps']} steps with control {list(ctl)}, {d['seconds']:.1f} s"}
 
 
 STAT_FIELDS = {"W": ([0], [1.0]), "U": ([1, 2, 3], [1.0] * 3), "omega": ([4], [1.0]), "psi": ([5], [1.0]),
@@ -215,6 +273,13 @@ def large_mixed_form(args):
         if k in MIXED_BYTES_PER_PARTICLE:
             gbs = MIXED_BYTES_PER_PARTICLE[k] * mean_live / (avg * 1e-3) / 1e9
             per[k].update({"GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+            tr = counter_traffic(k, True, COUNTERS_HUGE)
+            if tr is not None:   # the counters' launch time, not this run's
+                ms = measured(k, "avg_ms", True, COUNTERS_HUGE)
+                per[k].update({"counter_GB_per_launch": round(tr / 1e9, 3),
+                               "counter_bytes_per_particle": round(tr / mean_live, 1)})
+                if ms:
+                    per[k]["counter_GBs"] = round(tr / (ms * 1e-3) / 1e9, 1)
     out = {"workload": "cavity_huge", "triangles": mesh.n_elems, "particles": n0, "ppe": ini["ppe"],
            "bins": list(ini["bins"]), "control": list(ctl), "dt": dt, "steps": args.form_steps,
            "value": live / el, "ms_per_step": 1e3 * el / args.form_steps, "per_kernel": per}
@@ -384,28 +449,46 @@ def main():
     default = (args.nx, args.ny, args.ppe) == (400, 500, 200)
 
     def roofline(name):
-        if name not in kern or (name not in BYTES_PER_PARTICLE and name not in VALU_OPS_PER_PARTICLE):
+        if name not in kern or name not in BYTES_PER_PARTICLE:
             return None
         avg_ms = kern[name][0] / kern[name][1]
         traffic = counter_traffic(name, default)
+        hbm = BYTES_PER_PARTICLE[name] * mean_live / (avg_ms * 1e-3) / 1e9
         r = {"kernel": name, "avg_ms": round(avg_ms, 4),
-             "traffic": None if traffic is None else round(traffic / 1e9, 3), "traffic_unit": "GB per launch"}
-        if name in VALU_OPS_PER_PARTICLE:
-            ach = VALU_OPS_PER_PARTICLE[name] * mean_live / (avg_ms * 1e-3) / 1e12
+             "traffic": None if traffic is None else round(traffic / 1e9, 3), "traffic_unit": "GB per launch",
+             "hbm": {"bytes_per_particle": BYTES_PER_PARTICLE[name], "achieved_GBs": round(hbm, 1),
+                     "frac": round(hbm / HBM_PEAK_GBS, 4)}}
+        if traffic is not None:
+            tg = traffic / (avg_ms * 1e-3) / 1e9
+            r["hbm"].update(counter_GBs=round(tg, 1), counter_frac=round(tg / HBM_PEAK_GBS, 4),
+                            counter_bytes_per_particle=round(traffic / mean_live, 1))
+        valu = measured(name, "valu_per_wave", default)
+        if name == "advance" and valu is not None:
+            # one particle per lane: VALU lane-instructions per particle = instructions per wavefront
+            ach = valu * mean_live / (avg_ms * 1e-3) / 1e12
             r.update(bound="alu", achieved=round(ach, 2), peak=round(VALU_PEAK_TOPS, 2),
-                     unit="T FP64 lane-ops/s", frac=round(ach / VALU_PEAK_TOPS, 4),
-                     ops_per_particle=VALU_OPS_PER_PARTICLE[name])
-            hbm = BYTES_PER_PARTICLE[name] * mean_live / (avg_ms * 1e-3) / 1e9
-            r["hbm_GBs"] = round(hbm, 1)
-            r["hbm_frac"] = round(hbm / HBM_PEAK_GBS, 4)
+                     unit="T VALU lane-instructions/s", frac=round(ach / VALU_PEAK_TOPS, 4),
+                     valu_instructions_per_particle=valu, valu_busy=measured(name, "valu_busy", default))
+            flop = measured(name, "fp64_flop_per_particle", default)
+            if flop is not None:
+                fa = flop * mean_live / (avg_ms * 1e-3) / 1e12
+                r["fp64"] = {"flop_per_particle": flop, "achieved_TFLOPs": round(fa, 2), "peak_TFLOPs": FP64_PEAK_TFLOPS,
+                             "frac": round(fa / FP64_PEAK_TFLOPS, 4)}
         else:
-            ach = BYTES_PER_PARTICLE[name] * mean_live / (avg_ms * 1e-3) / 1e9
-            r.update(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                     frac=round(ach / HBM_PEAK_GBS, 4), bytes_per_particle=BYTES_PER_PARTICLE[name])
+            r.update(bound="hbm", achieved=r["hbm"]["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                     frac=r["hbm"]["frac"], bytes_per_particle=BYTES_PER_PARTICLE[name])
         return r
 
     dom = max(kern, key=lambda k: kern[k][0])
     roof = roofline(dom)
+    # the whole step against HBM: algorithmic bytes of its particle kernels per particle-step
+    step_bpp = sum(BYTES_PER_PARTICLE.values())
+    step_gbs = step_bpp * value / 1e9
+    step_roof = {"bytes_per_particle_step": step_bpp, "achieved_GBs": round(step_gbs, 1), "peak_GBs": HBM_PEAK_GBS,
+                 "frac": round(step_gbs / HBM_PEAK_GBS, 4), "target_frac": 0.6}
+    tr = [counter_traffic(k, default) for k in BYTES_PER_PARTICLE]
+    if all(t is not None for t in tr):
+        step_roof["counter_bytes_per_particle_step"] = round(sum(tr) / mean_live, 1)
     rooflines = [r for r in (roofline(k) for k in ("advance", "element_pass", "scatter")) if r]
     per_kernel = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches": v[1]} for k, v in kern.items()}
     for k, bpp in BYTES_PER_PARTICLE.items():
@@ -448,7 +531,8 @@ def main():
         "config": {"workload": "channel_large", "triangles": mesh.n_elems, "nodes": mesh.n_nodes,
                    "particles": n0, "ppe": args.ppe, "dt": dt, "control": list(ctl),
                    "bins": [4, 2, 2], "precision": "fp64", "parallelism": "single GPU"},
-        "roofline": roof, "rooflines": rooflines, "per_kernel": per_kernel, "cpu_baseline": cpu,
+        "roofline": roof, "rooflines": rooflines, "step_roofline": step_roof, "per_kernel": per_kernel,
+        "cpu_baseline": cpu,
         "forms": forms, "eulerian": eulerian,
     }
     print(json.dumps(out), flush=True)

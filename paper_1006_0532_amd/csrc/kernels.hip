@@ -411,10 +411,12 @@ __device__ __forceinline__ void particle_loop(const AdvanceArgs<R>& a)
     if (key >= 0) a.arrival[i] = arrival;
 }
 
-// One problem: three wavefronts per SIMD (at most 168 registers; the FP64 form spills a
-// few values of its cold paths).
+// One problem: three wavefronts per SIMD in the FP64 form (at most 168 registers; four
+// spill: 8.0 against 5.2 ms on the 8e7-particle channel), four in the mixed form (at most
+// 128 registers: 3.86 against 4.23 ms with three).
 template <class R, bool WPFULL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_advance(AdvanceArgs<R> a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == sizeof(float) ? 4 : 3)))
+k_advance(AdvanceArgs<R> a)
 {
     particle_loop<R, false, WPFULL>(a);
 }
