@@ -310,7 +310,8 @@ def mixed_error(mesh, f, mo, ini, dt, steps):
 def batched_form(args):
     """64 independent channel / street-canyon problems of uneven size (triangles
     log-uniform in [1e3, 2e5], 20-400 particles per element): advanced together (one
-    launch per kernel, graph-replayed steps, autotuned launch options) in FP64 and in the
+    launch per kernel, the particle loop's wavefronts across the ends of two problems in a
+    second small launch; graph-replayed steps, autotuned launch options) in FP64 and in the
     mixed form, against the same problems advanced one ensemble at a time (FP64)."""
     from paper_1006_0532_amd import pdfgpu, workloads as W
     probs = W.batched_problems(args.batched_problems)

@@ -31,6 +31,9 @@ struct AdvanceArgs {
     int32_t* arrival;           // [cap] rank of each particle among its new host's arrivals
     int32_t* wall_list;         // [cap] slots that take a new frequency (no-slip events)
     int32_t* wall_count;
+    int32_t* wave_list;         // [wave_cap] wavefronts whose lanes hold several problems
+    int32_t* wave_count;
+    int64_t wave_cap;
     int64_t ne;
     ProbParams p0;              // parameters of problem 0 (single-problem ensembles)
     const ProbParams* prm;      // [n_problems] (batched ensembles)

@@ -48,24 +48,31 @@ __device__ __noinline__ bool fallback_search(const ElemGeo* __restrict__ geo, co
     return false;
 }
 
+// Where the particle loop takes a particle's problem parameters from: the single problem's
+// copy in the kernel arguments, the table entry of each lane's problem, or the table entry
+// of the problem that all lanes of the wavefront share (a wave-uniform index, so the
+// parameters are scalar loads)
+enum { PM_ONE = 0, PM_LANE = 1, PM_WAVE = 2 };
+// The table is read through the constant address space: it does not change during the
+// loop, and through a generic pointer the compiler would have to assume that the loop's
+// own stores may overwrite it, and load the parameters into vector registers.
+typedef const __attribute__((address_space(4))) ProbParams ConstProb;
+
 struct AdvEvents {
     int ev_a, ev_b, omrefl, clamp, src, steps, refl, fb;
     int resample;   // the frequency is drawn again after the loop (no-slip event)
 };
 
-// One particle of the particle loop.  Returns its new host element (its old one when it
-// could not be tracked) and the particle's problem in prob.  R = double: FP64 throughout;
+// One particle of the particle loop with the parameters P of its problem.  Returns its new
+// host element (its old one when it could not be tracked).  R = double: FP64 throughout;
 // R = float: velocity, frequency and their SDEs in FP32, positions and tracking in FP64.
 // WPFULL: the nodal wp field has all nine components (stored by the elliptic-relaxation
 // solve); otherwise it is symmetric and the three lower components are not read
-template <class R, bool BATCHED, bool WPFULL>
+template <class R, bool WPFULL, class PP>
 __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const int64_t i, const int32_t e,
-                                               const uint32_t step, AdvEvents& ev, int& prob)
+                                               const uint32_t step, AdvEvents& ev, const PP& P)
 {
     using M = RMath<R>;
-    const ElemGeo* G = a.geo + e;
-    const ProbParams& P = BATCHED ? a.prm[G->prob] : a.p0;
-    prob = BATCHED ? G->prob : 0;
     const R nu = (R)P.m.nu, rho = (R)P.m.rho, C3 = (R)P.m.C3, C4 = (R)P.m.C4, CT = (R)P.m.CT,
             Cw1 = (R)P.m.Cw1, Cw2 = (R)P.m.Cw2;
     const R dt = (R)P.dt;
@@ -142,8 +149,9 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
     const R G21 = W21 * ik, G31 = W31 * ik, G32 = W32 * ik;
 
     // random numbers: 6 Gaussians and one uniform (Sec. 3.9)
-    const Words4 wA = rng_draw(P.key, pid, step, TAG_STEP, 0);
-    const Words4 wB = rng_draw(P.key, pid, step, TAG_STEP, 1);
+    const RngKey key{P.key.k0, P.key.k1};
+    const Words4 wA = rng_draw(key, pid, step, TAG_STEP, 0);
+    const Words4 wB = rng_draw(key, pid, step, TAG_STEP, 1);
     R z0, z1, z2, z3, z4, z5;
     M::normal2(wA.w0, wA.w1, z0, z1);
     M::normal2(wA.w2, wA.w3, z2, z3);
@@ -323,11 +331,12 @@ __device__ __forceinline__ void wave_events(const AdvEvents& ev, int v[NCOUNT])
 // Event counters: added to one of CNT_SLOTS spread copies per counter (no single hot
 // address).  One problem: one workgroup sum per counter.  Several problems: one sum per
 // wavefront whose lanes share a problem, single lanes otherwise.
-template <bool BATCHED>
-__device__ __forceinline__ void flush_events(unsigned long long* __restrict__ cnt, const AdvEvents& ev, int prob)
+template <int PM>
+__device__ __forceinline__ void flush_events(unsigned long long* __restrict__ cnt, const AdvEvents& ev, int prob,
+                                             const int64_t wave)
 {
     const int lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (!BATCHED) {
+    if (PM == PM_ONE) {
         __shared__ int wsum[4][NCOUNT];
         int v[NCOUNT];
         wave_events(ev, v);
@@ -345,8 +354,8 @@ __device__ __forceinline__ void flush_events(unsigned long long* __restrict__ cn
     const unsigned long long act = __ballot(prob >= 0);
     if (!act) return;
     const int p0 = __shfl(prob, __ffsll((long long)act) - 1);
-    const int slot = (int)((blockIdx.x * (unsigned)nw + (unsigned)wid) & (CNT_SLOTS - 1));
-    if (!__ballot(prob >= 0 && prob != p0)) {
+    const int slot = (int)(wave & (CNT_SLOTS - 1));
+    if (PM == PM_WAVE || !__ballot(prob >= 0 && prob != p0)) {
         int v[NCOUNT];
         wave_events(ev, v);
         if (lane < NCOUNT && v[lane])
@@ -377,23 +386,53 @@ __device__ __forceinline__ HostCount count_new_hosts(int32_t* __restrict__ count
 }
 __device__ __forceinline__ int arrival_rank(const HostCount& h) { return __shfl(h.base, h.leader) + h.rank; }
 
-// Particle loop: one thread per used slot (merged particles are dead slots, elem < 0)
-template <class R, bool BATCHED, bool WPFULL>
-__device__ __forceinline__ void particle_loop(const AdvanceArgs<R>& a)
+// One slot of the particle loop (merged particles are dead slots, elem < 0); i is the slot
+// index of the lane, slots beyond the used ones are idle lanes.  PM_WAVE: a wavefront whose
+// live lanes hold more than one problem does nothing here and is listed for
+// k_advance_mixed_waves, which runs it with PM_LANE.
+template <class R, int PM, bool WPFULL>
+__device__ __forceinline__ void particle_slot(const AdvanceArgs<R>& a, const int64_t i)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nslots = a.meta[0];
     const uint32_t step = (uint32_t)a.meta[4];
     int32_t key = -1;
     int prob = -1;
     AdvEvents ev = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t e = -1;
     if (i < nslots) {
-        int32_t e = a.s.elem[i];
+        e = a.s.elem[i];
         if (e >= a.ne) {
             atomicOr(a.err, ERR_BADELEM);
             e = -1;
         }
-        if (e >= 0) key = advance_one<R, BATCHED, WPFULL>(a, i, e, step, ev, prob);
+        if constexpr (PM == PM_ONE) {
+            if (e >= 0) {
+                key = advance_one<R, WPFULL>(a, i, e, step, ev, a.p0);
+                prob = 0;
+            }
+        } else if constexpr (PM == PM_LANE) {
+            if (e >= 0) {
+                prob = a.geo[e].prob;
+                key = advance_one<R, WPFULL>(a, i, e, step, ev, *(ConstProb*)(a.prm + prob));
+            }
+        }
+    }
+    if (PM == PM_WAVE) {
+        const int pl = e >= 0 ? a.geo[e].prob : -1;
+        const unsigned long long act = __ballot(pl >= 0);
+        const int pu = act ? __builtin_amdgcn_readfirstlane(__shfl(pl, __ffsll((long long)act) - 1)) : 0;
+        if (__ballot(pl >= 0 && pl != pu)) {
+            if (lane_id() == 0) {
+                const int k = atomicAdd(a.wave_count, 1);
+                if (k < a.wave_cap) a.wave_list[k] = (int32_t)(i >> 6);
+                else atomicOr(a.err, ERR_CAPACITY);
+            }
+            return;
+        }
+        if (e >= 0) {
+            key = advance_one<R, WPFULL>(a, i, e, step, ev, *(ConstProb*)(a.prm + pu));
+            prob = pu;
+        }
     }
     // slots whose frequency is drawn again: one atomic per wavefront
     const unsigned long long rm = __ballot(ev.resample != 0);
@@ -406,7 +445,7 @@ __device__ __forceinline__ void particle_loop(const AdvanceArgs<R>& a)
     }
     // the counting atomic is in flight while the event counters are flushed
     const HostCount hc = count_new_hosts(a.counts, key);
-    flush_events<BATCHED>(a.cnt, ev, prob);
+    flush_events<PM>(a.cnt, ev, prob, i >> 6);
     const int arrival = arrival_rank(hc);
     if (key >= 0) a.arrival[i] = arrival;
 }
@@ -418,14 +457,27 @@ template <class R, bool WPFULL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == sizeof(float) ? 4 : 3)))
 k_advance(AdvanceArgs<R> a)
 {
-    particle_loop<R, false, WPFULL>(a);
+    particle_slot<R, PM_ONE, WPFULL>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// Several problems: per-particle problem parameters from the table
+// Several problems: the wavefronts whose lanes share one problem (all but those across the
+// ends of the problems' slot ranges, and some among the clones of number control) read its
+// parameters as scalars, which keeps the register budget of the one-problem loop
 template <class R>
-__global__ void __launch_bounds__(256) k_advance_batched(AdvanceArgs<R> a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == sizeof(float) ? 4 : 3)))
+k_advance_batched(AdvanceArgs<R> a)
 {
-    particle_loop<R, true, false>(a);
+    particle_slot<R, PM_WAVE, false>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ... and the listed wavefronts with each lane's parameters from the table (one wavefront per
+// workgroup, grid-stride over the list)
+template <class R>
+__global__ void __launch_bounds__(64) k_advance_mixed_waves(AdvanceArgs<R> a)
+{
+    const int n = (int)min((int64_t)*a.wave_count, a.wave_cap);
+    for (int w = blockIdx.x; w < n; w += gridDim.x)
+        particle_slot<R, PM_LANE, false>(a, (int64_t)a.wave_list[w] * 64 + threadIdx.x);
 }
 
 // Eq. (58) for the particles of the last no-slip events: omega ~ Gamma(1/C4) with the mean
@@ -1461,6 +1513,7 @@ __global__ void __launch_bounds__(256) k_node_finalize(NodeArgs<R> a)
         if (a.advance_step) a.meta[4] += 1;   // step counter of the random streams
         a.big_count[0] = 0;          // worklist of large elements, empty for the next pass
         a.big_count[1] = 0;          // list of no-slip resamples, empty for the next step
+        a.big_count[2] = 0;          // list of wavefronts with several problems, the same
     }
     if (i >= a.nn) return;
     if (a.estimator == 1) {
@@ -1967,9 +2020,11 @@ void launch_advance(const AdvanceArgs<R>& a, int64_t n_ub, bool batched, bool wp
 {
     if (n_ub <= 0) return;
     if (block != 64 && block != 128) block = 256;
-    if (batched)
+    if (batched) {
         hipLaunchKernelGGL(k_advance_batched<R>, dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
-    else if (wp_full)
+        const int64_t waves = (n_ub + 63) / 64;
+        hipLaunchKernelGGL(k_advance_mixed_waves<R>, dim3((unsigned)std::min<int64_t>(waves, 1024)), dim3(64), 0, s, a);
+    } else if (wp_full)
         hipLaunchKernelGGL((k_advance<R, true>), dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
     else
         hipLaunchKernelGGL((k_advance<R, false>), dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);

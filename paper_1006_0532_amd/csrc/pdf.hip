@@ -219,6 +219,9 @@ pdf_status step_once(pdf_ens_s* E, hipStream_t s)
     a.arrival = E->arrival;
     a.wall_list = E->idx;          // free between the particle loop and the scatter
     a.wall_count = E->big_count + 1;
+    a.wave_list = E->wave_list;
+    a.wave_count = E->big_count + 2;
+    a.wave_cap = E->n_problems > 1 ? E->cap / 64 + 2 : 0;
     a.ne = g.ne;
     a.p0 = E->h_prm[0];
     a.prm = E->d_prm;
@@ -1118,7 +1121,7 @@ pdf_status pdf_ens_destroy(pdf_ens E)
     dfree(E->counts); dfree(E->start); dfree(E->idx); dfree(E->arrival); dfree(E->scan_tmp); dfree(E->d_meta); free_raw(E->part);
     dfree(E->stats); free_raw(E->shift); dfree(E->tm); dfree(E->err); dfree(E->cnt); dfree(E->gkey); dfree(E->gord);
     dfree(E->gu3); dfree(E->ctl_clone); dfree(E->ctl_off); dfree(E->ctl_rep); dfree(E->big_list);
-    dfree(E->big_count); dfree(E->d_prm); dfree(E->d_scalar);
+    dfree(E->big_count); dfree(E->wave_list); dfree(E->d_prm); dfree(E->d_scalar);
     free_devgrid(E->dg);
     dfree(E->fb_gn);
     dfree(E->fb_h);
@@ -1275,7 +1278,8 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
     if (st == PDF_OK) st = dalloc(&E->ctl_off, g.ne + 1);
     if (st == PDF_OK) st = dalloc(&E->ctl_rep, 4);
     if (st == PDF_OK) st = dalloc(&E->big_list, g.ne);
-    if (st == PDF_OK) st = dalloc(&E->big_count, 2);
+    if (st == PDF_OK) st = dalloc(&E->big_count, 3);
+    if (st == PDF_OK && n_problems > 1) st = dalloc(&E->wave_list, cap / 64 + 2);
     if (st != PDF_OK) {
         pdf_ens_destroy(E);
         return st;
@@ -1299,7 +1303,7 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
         return st;
     }
     launch_fill_i32(E->counts, g.ne, 0, s);
-    launch_fill_i32(E->big_count, 2, 0, s);
+    launch_fill_i32(E->big_count, 3, 0, s);
     launch_fill_i32(E->idx, cap, 0, s);
     launch_fill_u64(E->cnt, (int64_t)n_problems * NCOUNT * CNT_SLOTS, 0ull, s);
     launch_fill_i32(reinterpret_cast<int32_t*>(E->err), 1, 0, s);

@@ -195,6 +195,41 @@ def test_batched_problems_match_the_oracle(gpu):
         _say(f"  problem {p}: {rep}")
 
 
+def test_batched_ragged_problems_match_the_oracle(gpu):
+    """Problems whose particle counts are not multiples of the wavefront size, so that
+    wavefronts hold particles of two problems from the first step on (the particle loop
+    runs those with per-lane parameters), and clones of every problem after number control."""
+    _say("test_batched_ragged_problems_match_the_oracle")
+    probs = []
+    for (m, f, mo, ini, dt), ppe in zip(_problems(), (41, 59, 203)):
+        d = dict(ini)
+        d["ppe"] = ppe
+        probs.append((m, f, mo, d, dt))
+    ends = np.cumsum([len(m.tri) * ini["ppe"] for m, f, mo, ini, dt in probs])
+    assert all(int(x) % 64 for x in ends[:-1])
+    grids = [gpu.Grid(m, f, mo) for m, f, mo, ini, dt in probs]
+    ge = gpu.Ensemble(grids, [ini for m, f, mo, ini, dt in probs])
+    orc = [_oracle_for(p, m, f, mo, ini) for p, (m, f, mo, ini, dt) in enumerate(probs)]
+    dts = [dt for *_, dt in probs]
+    for n in range(6):
+        ge.step(dts)
+        for (og, oe), dt in zip(orc, dts):
+            oe.step(dt)
+        if n in (1, 3):
+            rg = ge.control(45, 70)
+            ro = [oe.control(45, 70) for og, oe in orc]
+            for k in rg:
+                assert rg[k] == sum(r[k] for r in ro), (k, rg, ro)
+    for p, ((m, f, mo, ini, dt), (og, oe)) in enumerate(zip(probs, orc)):
+        assert ge.count(p) == oe.count()
+        frame = og.export()["frame"]
+        rep, excl = compare_states(ge.export(problem=p), oe.export(), frame, _length(m))
+        skip = set(m.tri[list(excl)].ravel().tolist()) if excl else set()
+        compare_stats(ge.stats(p), oe.stats(), skip)
+        assert ge.counters(p) == oe.counters(), p
+        _say(f"  problem {p}: {rep}")
+
+
 def test_batched_equals_single_problem_ensembles(gpu):
     """Problem p of a batch is the single-problem ensemble with seed ^ (p << 32): the same
     particles in the same elements, equal to rounding (the two particle-loop kernels read
