@@ -94,6 +94,7 @@ enum { PDF_COND_BINS = 0, PDF_COND_PROJECTION = 1 };
 enum { PDF_EDGE_INTERIOR = 0, PDF_EDGE_WALL = 1, PDF_EDGE_SLIP = 2, PDF_EDGE_PERIODIC = 3 };
 
 #define PDF_NSTAT 13     /* statistics per node, see pdf_stats */
+#define PDF_STATS_ALL 0x1FFFu  /* stat_mask selecting all PDF_NSTAT statistics */
 #define PDF_NCOUNTERS 8  /* event counters, see pdf_counters */
 #define PDF_NTIMERS 12   /* kernel timers, see pdf_timing */
 
@@ -204,14 +205,17 @@ pdf_status pdf_ens_destroy(pdf_ens ens);
  * steps. */
 pdf_status pdf_step(pdf_ens ens, const double* dt, int32_t n_steps, void* hip_stream);
 
-/* Nodal statistics of the last step (Sec. 3.3) of one problem, out = [n_nodes][13]:
+/* Nodal statistics of the last step (Sec. 3.3) of one problem.  Statistic j (0..12) is
  *   W = sum_p w_p N_n(x_p), <U1>, <U2>, <U3>, <omega>, <psi>,
  *   <u1u1>, <u2u2>, <u3u3>, <u1u2>, <u1u3>, <u2u3>, <psi'psi'>
  * over the particles of the elements around node n, weighted by w_p N_n(x_p); the
  * second moments are about the node's own means (NaN where W = 0).
+ * stat_mask: bit j selects statistic j (PDF_STATS_ALL: all 13); out = [n_nodes][k] with the
+ * k selected statistics in ascending j.  A mask that selects none or has bits above 12 is
+ * PDF_E_INVAL.
  * out_is_device != 0: out is a device pointer and the copy is enqueued on hip_stream;
  * otherwise out is host memory and the call synchronises. */
-pdf_status pdf_stats(pdf_ens ens, int32_t problem, double* out, int32_t out_is_device,
+pdf_status pdf_stats(pdf_ens ens, int32_t problem, uint32_t stat_mask, double* out, int32_t out_is_device,
                      void* hip_stream);
 
 /* Per-element particle-number control (Sec. 3.7, App. B) on the canonical order of the

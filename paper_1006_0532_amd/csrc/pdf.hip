@@ -1379,23 +1379,55 @@ pdf_status pdf_sync(pdf_ens E)
     return check_device_error(E);
 }
 
-pdf_status pdf_stats(pdf_ens E, int32_t problem, double* out, int32_t out_is_device, void* hip_stream)
+// the selected columns of the statistics of nodes [0, nn) into out[nn][k]
+__global__ void __launch_bounds__(256) k_stats_select(const double* __restrict__ src, int64_t nn, uint32_t mask,
+                                                     int k, double* __restrict__ out)
 {
-    if (!E || !out || problem < 0 || problem >= E->n_problems) {
-        set_error("pdf_stats: invalid argument");
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nn * k) return;
+    const int64_t n = i / k;
+    int c = (int)(i - n * k), j = 0;
+    for (;; ++j)
+        if (((mask >> j) & 1u) && c-- == 0) break;
+    out[i] = src[n * NSTAT + j];
+}
+
+pdf_status pdf_stats(pdf_ens E, int32_t problem, uint32_t stat_mask, double* out, int32_t out_is_device,
+                     void* hip_stream)
+{
+    if (!E || !out || problem < 0 || problem >= E->n_problems || stat_mask == 0u ||
+        (stat_mask & ~(uint32_t)PDF_STATS_ALL) != 0u) {
+        set_error("pdf_stats: invalid argument (problem, output or stat_mask)");
         return PDF_E_INVAL;
     }
     HIP_TRY(hipSetDevice(E->grid->device));
     hipStream_t s = as_stream(hip_stream);
     const ProbParams& P = E->h_prm[problem];
-    const size_t bytes = sizeof(double) * (size_t)P.nn * NSTAT;
+    const int k = __builtin_popcount(stat_mask);
     const double* src = E->stats + P.noff * NSTAT;
     if (out_is_device) {
-        HIP_TRY(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToDevice, s));
+        if (k == NSTAT) {
+            HIP_TRY(hipMemcpyAsync(out, src, sizeof(double) * (size_t)P.nn * NSTAT, hipMemcpyDeviceToDevice, s));
+        } else if (P.nn > 0) {
+            hipLaunchKernelGGL(k_stats_select, dim3((unsigned)((P.nn * k + 255) / 256)), dim3(256), 0, s, src, P.nn,
+                               stat_mask, k, out);
+            HIP_TRY(hipGetLastError());
+        }
         return PDF_OK;
     }
-    HIP_TRY(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToHost, s));
+    if (k == NSTAT) {
+        HIP_TRY(hipMemcpyAsync(out, src, sizeof(double) * (size_t)P.nn * NSTAT, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return check_device_error(E);
+    }
+    std::vector<double> all((size_t)P.nn * NSTAT);
+    HIP_TRY(hipMemcpyAsync(all.data(), src, sizeof(double) * all.size(), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t n = 0; n < P.nn; ++n) {
+        int c = 0;
+        for (int j = 0; j < NSTAT; ++j)
+            if ((stat_mask >> j) & 1u) out[n * k + c++] = all[(size_t)n * NSTAT + j];
+    }
     return check_device_error(E);
 }
 

@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("PDFGPU_LIB") or os.path.join(HERE, "libpdfgpu.so")
 
 PDF_NSTAT = 13
+PDF_STATS_ALL = (1 << PDF_NSTAT) - 1   # stat_mask selecting every statistic
 PDF_NCOUNTERS = 8
 PDF_NTIMERS = 12
 TIMER_NAMES = ["init", "advance", "scan", "scatter", "element_pass", "node_finalize",
@@ -93,7 +94,7 @@ def load(path: str = LIB_PATH):
         "pdf_particles_init": [C.POINTER(vp), C.POINTER(InitDesc), C.c_int32, vp, C.POINTER(vp)],
         "pdf_ens_destroy": [vp],
         "pdf_step": [vp, dp, C.c_int32, vp],
-        "pdf_stats": [vp, C.c_int32, vp, C.c_int32, vp],
+        "pdf_stats": [vp, C.c_int32, C.c_uint32, vp, C.c_int32, vp],
         "pdf_control": [vp, C.c_int32, C.c_int32, C.POINTER(ControlReport), vp],
         "pdf_count": [vp, C.c_int32, i64p],
         "pdf_particles_export": [vp, C.c_int32, C.c_int64, dp, dp, dp, dp, dp, dp, u64p, ip, i64p, vp],
@@ -228,13 +229,16 @@ class Ensemble:
     def sync(self):
         _check(load().pdf_sync(self.h))
 
-    def stats(self, problem: int = 0) -> np.ndarray:
-        out = np.empty((self.grids[problem].nn, PDF_NSTAT))
-        _check(load().pdf_stats(self.h, int(problem), out.ctypes.data_as(C.c_void_p), 0, C.c_void_p(self.stream)))
+    def stats(self, problem: int = 0, mask: int = PDF_STATS_ALL) -> np.ndarray:
+        """Nodal statistics [n_nodes][k] of the statistics whose bits are set in mask."""
+        k = bin(int(mask) & PDF_STATS_ALL).count("1") or 1
+        out = np.empty((self.grids[problem].nn, k))
+        _check(load().pdf_stats(self.h, int(problem), int(mask), out.ctypes.data_as(C.c_void_p), 0,
+                                C.c_void_p(self.stream)))
         return out
 
-    def stats_device(self, ptr: int, problem: int = 0):
-        _check(load().pdf_stats(self.h, int(problem), C.c_void_p(ptr), 1, C.c_void_p(self.stream)))
+    def stats_device(self, ptr: int, problem: int = 0, mask: int = PDF_STATS_ALL):
+        _check(load().pdf_stats(self.h, int(problem), int(mask), C.c_void_p(ptr), 1, C.c_void_p(self.stream)))
 
     # check=False: a sticky device error does not raise; its status is kept in
     # self.last_status and the call's outputs (filled before the error is reported) are

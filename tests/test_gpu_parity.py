@@ -55,6 +55,32 @@ def test_init_parity(gpu):
     compare_stats(ge.stats(), oe.stats())
 
 
+def test_stats_mask_selects_columns(gpu):
+    """pdf_stats with a stat_mask returns the selected columns of the full statistics in
+    ascending order, bit for bit, to host and to device memory; empty and out-of-range
+    masks are argument errors."""
+    import torch
+    _say("test_stats_mask_selects_columns")
+    mesh, f, mo, ini = W.channel_small(nx=12, ny=10)
+    ge = gpu.Ensemble(gpu.Grid(mesh, f, mo), ini)
+    ge.step(1e-3, 2)
+    full = ge.stats()
+    assert full.shape == (mesh.n_nodes, gpu.PDF_NSTAT)
+    rng = np.random.default_rng(5)
+    masks = [1, 1 << 12, 0b1010101, gpu.PDF_STATS_ALL] + [int(m) for m in rng.integers(1, 1 << 13, 4)]
+    for m in masks:
+        cols = [j for j in range(gpu.PDF_NSTAT) if (m >> j) & 1]
+        host = ge.stats(mask=m)
+        assert np.array_equal(host, full[:, cols], equal_nan=True), m
+        dev = torch.full((mesh.n_nodes, len(cols)), -7.0, dtype=torch.float64, device="cuda")
+        ge.stats_device(dev.data_ptr(), mask=m)
+        ge.sync()
+        assert np.array_equal(dev.cpu().numpy(), full[:, cols], equal_nan=True), m
+    for bad in (0, 1 << 13, gpu.PDF_STATS_ALL | (1 << 20)):
+        with pytest.raises(gpu.PdfError):
+            ge.stats(mask=bad)
+
+
 @pytest.mark.parametrize("steps", [1, 20])
 def test_channel_small_step_parity(gpu, steps):
     """Full step (advance, track, group, bin, mix, statistics) every step, 2e5 particles."""
