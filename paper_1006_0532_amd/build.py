@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdfgpu.so")
-SOURCES = ["kernels.hip", "fem.hip", "amg.hip", "pdf.hip", "noalloc.hip", "grid.cpp"]
+SOURCES = ["kernels.hip", "fem.hip", "amg.hip", "pdf.hip", "noalloc.hip", "redist.hip", "grid.cpp"]
 ARCH = os.environ.get("PDF_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1,5 +1,7 @@
 // C ABI of libpdfgpu (include/pdf.h): argument checks, device memory, and the order of the
-// kernel launches of one time step.  All arithmetic of the method runs in kernels.hip.
+// kernel launches of one time step.  The arithmetic of the method runs in the kernels of
+// kernels.hip (the step), redist.hip (App. B), fem.hip and amg.hip (the Eulerian solves) and
+// noalloc.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +24,8 @@ using namespace pdfgpu;
 namespace pdfgpu {
 pdf_status build_grid(pdf_grid_s& g, const pdf_mesh_desc& m, const pdf_fields_desc& f);
 double* noalloc_scratch(int device);
+pdf_status redistribution_plan(pdf_ens_s* E, const std::vector<int>& problems, int32_t n_min, uint32_t step,
+                               int32_t** plan_buf, int64_t* plan_cap, int64_t* total, hipStream_t s);
 
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -924,106 +928,16 @@ FemOp fem_op(pdf_ens_s* E, double mass, double stiff, const double* L2, const ui
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
-// Particle redistribution (App. B).  The moves are inherently serial (each one changes the
-// counts that select the next), so the host plans them from the element counts: an ordered
-// set of (count, element) finds the emptiest and the fullest element with ties to the
-// lowest index, and only the elements that take part keep explicit slot lists.  A slot
-// that moves several times, or copies a slot that moved before, is resolved to the
-// original slots its final position and properties come from, so that the device applies
-// all moves at once from the state of the last step.
+// Particle redistribution (App. B): planned on the device (redist.hip), applied here from
+// the state of the last step by gathering every move's sources into the idle state buffer,
+// then writing them.
 // ---------------------------------------------------------------------------------------
 namespace {
 
-constexpr uint32_t TAG_REDIST = 5;
-
-struct RedistSrc {
-    int32_t pos;    // slot whose position is taken, or -(e + 1): centroid of element e
-    int32_t prop;   // slot whose velocity, frequency and scalar are taken
-    int32_t elem;
-};
-
-int64_t plan_redistribution(const ProbParams& P, int32_t n_min, uint32_t step, const std::vector<int32_t>& start,
-                            std::unordered_map<int32_t, RedistSrc>& moved)
-{
-    const int64_t ne = P.ne, e0 = P.eoff;
-    std::vector<int64_t> cnt(ne);
-    int64_t lo = INT64_MAX, hi = INT64_MIN;
-    for (int64_t e = 0; e < ne; ++e) {
-        cnt[e] = (int64_t)start[e0 + e + 1] - start[e0 + e];
-        lo = std::min(lo, cnt[e]);
-        hi = std::max(hi, cnt[e]);
-    }
-    if (ne == 0 || lo >= n_min || hi - lo <= 1) return 0;
-    std::set<std::pair<int64_t, int64_t>> order;
-    for (int64_t e = 0; e < ne; ++e) order.insert({cnt[e], e});
-    std::unordered_map<int64_t, std::vector<int32_t>> lists;
-    auto list_of = [&](int64_t e) -> std::vector<int32_t>& {
-        auto it = lists.find(e);
-        if (it != lists.end()) return it->second;
-        std::vector<int32_t>& v = lists[e];
-        for (int32_t q = start[e0 + e]; q < start[e0 + e + 1]; ++q) v.push_back(q);
-        return v;
-    };
-    auto source = [&](int32_t slot) {
-        auto it = moved.find(slot);
-        return it != moved.end() ? it->second : RedistSrc{slot, slot, -1};
-    };
-    int64_t k = 0;
-    for (;;) {
-        const auto mn = *order.begin();
-        const int64_t cmax = order.rbegin()->first;
-        const auto mx = *order.lower_bound({cmax, INT64_MIN});
-        if (mn.first >= n_min || cmax - mn.first <= 1) break;
-        const int64_t mine = mn.second, maxe = mx.second;
-        const Words4 w = philox4x32_10((uint32_t)k, (uint32_t)((uint64_t)k >> 32), step, TAG_REDIST << 16, P.key.k0,
-                                       P.key.k1);
-        std::vector<int32_t>& give = list_of(maxe);
-        const int64_t r = (int64_t)(u01(w.w0) * (double)give.size());
-        const int32_t slot = give[r];
-        give.erase(give.begin() + r);
-        std::vector<int32_t>& take = list_of(mine);
-        RedistSrc ns;
-        if (!take.empty()) {
-            const int64_t d = (int64_t)(u01(w.w1) * (double)take.size());
-            ns = source(take[d]);
-        } else {
-            ns = source(slot);
-            ns.pos = -(int32_t)(e0 + mine) - 1;
-        }
-        ns.elem = (int32_t)(e0 + mine);
-        moved[slot] = ns;
-        take.push_back(slot);
-        order.erase(mn);
-        order.erase(mx);
-        order.insert({mn.first + 1, mine});
-        order.insert({mx.first - 1, maxe});
-        ++k;
-    }
-    return k;
-}
-
 template <class R>
-pdf_status apply_redistribution(pdf_ens_s* E, const std::unordered_map<int32_t, RedistSrc>& moved, hipStream_t s)
+pdf_status apply_redistribution(pdf_ens_s* E, int64_t m, hipStream_t s)
 {
-    const int64_t m = (int64_t)moved.size();
     if (m == 0) return PDF_OK;
-    if (m > E->redist_cap) {
-        dfree(E->redist_plan);
-        E->redist_cap = 0;
-        pdf_status st = dalloc(&E->redist_plan, 4 * m);
-        if (st != PDF_OK) return st;
-        E->redist_cap = m;
-    }
-    std::vector<int32_t> plan;
-    plan.reserve(4 * m);
-    for (const auto& kv : moved) {
-        plan.push_back(kv.first);
-        plan.push_back(kv.second.pos);
-        plan.push_back(kv.second.prop);
-        plan.push_back(kv.second.elem);
-    }
-    HIP_TRY(hipMemcpyAsync(E->redist_plan, plan.data(), sizeof(int32_t) * plan.size(), hipMemcpyHostToDevice, s));
-    // the other state buffer is free between steps: it stages the gathered states
     launch_redistribute<R>(cur(E).as<R>(), E->buf[1 - E->cur].as<R>(), E->redist_plan, E->dg.geo, m, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
@@ -1445,22 +1359,20 @@ pdf_status pdf_redistribute(pdf_ens E, int32_t problem, int32_t n_min, int64_t* 
         set_error("pdf_redistribute: no element pass since the last control or redistribution");
         return PDF_E_STATE;
     }
-    const int64_t ne = E->dg.ne;
-    std::vector<int32_t> start(ne + 1);
     int64_t meta[5];
-    HIP_TRY(hipMemcpyAsync(start.data(), E->start, sizeof(int32_t) * (ne + 1), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(meta, E->d_meta, sizeof(meta), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     E->step = meta[4];   // the device's step counter (steps replayed from a caller's graph included)
     pdf_status st = check_device_error(E);
     if (st != PDF_OK) return st;
-    std::unordered_map<int32_t, RedistSrc> moved;
-    int64_t total = 0;
+    std::vector<int> probs;
     for (int p = 0; p < E->n_problems; ++p)
-        if (problem < 0 || p == problem)
-            total += plan_redistribution(E->h_prm[p], n_min, (uint32_t)E->step, start, moved);
-    st = E->precision == PDF_MIXED ? apply_redistribution<float>(E, moved, s)
-                                   : apply_redistribution<double>(E, moved, s);
+        if (problem < 0 || p == problem) probs.push_back(p);
+    int64_t total = 0;
+    st = redistribution_plan(E, probs, n_min, (uint32_t)E->step, &E->redist_plan, &E->redist_cap, &total, s);
+    if (st != PDF_OK) return st;
+    st = E->precision == PDF_MIXED ? apply_redistribution<float>(E, total, s)
+                                   : apply_redistribution<double>(E, total, s);
     if (st != PDF_OK) return st;
     if (total > 0) E->ctl_valid = false;
     if (moves_out) *moves_out = total;

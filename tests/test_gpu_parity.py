@@ -653,6 +653,47 @@ def test_redistribution_batched(gpu):
             assert not excl
 
 
+def test_redistribution_skewed_counts_parity(gpu):
+    """App. B on element counts spread over many levels on both sides (empty elements,
+    elements of more than 100 particles whose departures span several 32-slot words):
+    the same moves as the oracle's serial loop, for two thresholds in a row."""
+    _say("test_redistribution_skewed_counts_parity")
+    mesh = box(6, 6, length=2.0, seed=23)
+    f = W.uniform_fields(mesh, mean_u=(0.2, 0.0, 0.0), mean_omega=1.0)
+    mo = W.model_constants(nu=1.0e-4)
+    ini = W.init_desc(ppe=30, u_sigma=0.3, src_r=0.0, bins=(2, 2, 1), seed=0xABB)
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    st = oe.export()
+    n, ne = len(st["x"]), mesh.n_elems
+    rng = np.random.default_rng(41)
+    wgt = np.array([(e % 7) ** 3 for e in range(ne)], float)
+    cnt = rng.multinomial(n, wgt / wgt.sum())
+    assert cnt.max() > 100 and (cnt == 0).sum() >= 8
+    elem = np.repeat(np.arange(ne, dtype=np.int32), cnt)
+    a, b = rng.random(n), rng.random(n)
+    flip = a + b > 1.0
+    a[flip], b[flip] = 1.0 - a[flip], 1.0 - b[flip]
+    v = frame[elem].reshape(n, 3, 2)
+    xy = v[:, 0] + a[:, None] * (v[:, 1] - v[:, 0]) + b[:, None] * (v[:, 2] - v[:, 0])
+    st["x"], st["y"], st["elem"] = np.mod(xy[:, 0], mesh.period_x), xy[:, 1], elem
+    nxt = int(st["pid"].max()) + 1
+    oe.import_state(st, step=3, next_pid=nxt)
+    ge.import_state(st, step=3, next_pid=nxt)
+    compare_states(ge.export(), oe.export(), frame, _length(mesh))
+    total = 0
+    for n_min in (45, 70):
+        mo_, mg = oe.redistribute(n_min), ge.redistribute(n_min)
+        assert mo_ == mg and mg > 0, (n_min, mo_, mg)
+        total += mg
+        rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh))
+        assert not excl
+        oe.step(0.01)
+        ge.step(0.01)
+        compare_states(ge.export(), oe.export(), frame, _length(mesh))
+    assert total > 1000
+
+
 @pytest.mark.parametrize("nc", [5, 20])
 def test_projection_conditioning_parity(gpu, nc):
     """Fox's projection (Eqs. 64-66) in place of the sort-and-divide bins, with number
