@@ -288,12 +288,14 @@ pdf_status pdf_set_feedback(pdf_ens ens, int32_t enable, double alpha, int32_t f
  * uniformly among the receiving element's current particles, or, when that element is
  * empty, keeps its properties and sits at the element's centroid.  Move k of a problem
  * draws one Philox block with the problem's key and counter (k, step, tag 5).  Particle
- * count, pids and total weight do not change.  The moves are planned serially on the host
- * from the element counts (one device-to-host copy of the segment starts) and applied by
- * two device kernels; a later pdf_control needs another step first.  *moves_out (may be
- * NULL) receives the number of moves.  Synchronises.
+ * count, pids and total weight do not change.  The moves are planned on the device (the
+ * host reads two small per-problem summaries: the count extremes and the level histograms)
+ * and applied by two device kernels; a later pdf_control needs another step first.
+ * *moves_out (may be NULL) receives the number of moves.  Synchronises.
  * Errors: PDF_E_INVAL (n_min < 0, bad problem), PDF_E_STATE (no step since the last
- * control or redistribution), PDF_E_NOMEM, PDF_E_HIP. */
+ * control or redistribution), PDF_E_CAPACITY (a problem whose counts span more than 2^22
+ * levels on the giving side, or whose level table exceeds 2^27 entries), PDF_E_NOMEM,
+ * PDF_E_HIP. */
 pdf_status pdf_redistribute(pdf_ens ens, int32_t problem, int32_t n_min, int64_t* moves_out,
                             void* hip_stream);
 
