@@ -726,10 +726,19 @@ __device__ __forceinline__ double mix_fraction(int32_t mix, double dt, double tm
     return f > 1.0 ? 1.0 : f;
 }
 
+// Plain running sum (the few particles of one lane of the element pass; the lanes' sums are
+// then added with the precision's Acc)
+template <class R>
+struct LaneSum {
+    R s = R(0);
+    __device__ void add(R v) { s += v; }
+    __device__ R value() const { return s; }
+};
+
 // Per-vertex partial sums of one particle (Sec. 3.3): weight, shifted first moments and
 // shifted products, accumulated with shape-function weight w * lambda_v.
-template <class R>
-__device__ __forceinline__ void add_partials(Acc<R> (&acc)[3][NPART], const R (&rs)[3][5], const R lam[3], R w,
+template <class R, class A>
+__device__ __forceinline__ void add_partials(A (&acc)[3][NPART], const R (&rs)[3][5], const R lam[3], R w,
                                              R u0, R u1, R u2, R om, R psi)
 {
     const R q5[5] = {u0, u1, u2, om, psi};
@@ -1078,6 +1087,14 @@ struct WaveBlock {
     static constexpr int waves = 2;
     static constexpr int per_simd = PPL <= 5 ? 4 : 1;
 };
+// Wavefronts per SIMD of a tier: FP32 state with at most four particles per lane fits 96
+// registers, five wavefronts (3.55 -> 3.37 ms on the 8e7-particle channel; the LDS of a
+// workgroup allows five); the projection's extra registers would spill there
+template <int PPL, class R, bool PROJ>
+constexpr int element_wave_occupancy()
+{
+    return sizeof(R) == sizeof(float) && PPL <= 4 && !PROJ ? 5 : WaveBlock<PPL>::per_simd;
+}
 
 // One wavefront per element (up to 64*PPL particles, PPL per lane).  Lanes own particles
 // in load order while the three sort levels rank (U_l, pid) keys staged in LDS; then each
@@ -1087,7 +1104,7 @@ struct WaveBlock {
 // (n_below = -1 for the first tier, so empty elements are handled there); the last tier
 // puts larger elements on the workgroup kernel's worklist (last != 0).
 template <int PPL, class R, bool PROJ>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WaveBlock<PPL>::per_simd)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(element_wave_occupancy<PPL, R, PROJ>())))
 k_element_wave(ElementArgs<R> a, int n_below, int last)
 {
     constexpr int N = 64 * PPL;
@@ -1371,12 +1388,13 @@ k_element_wave(ElementArgs<R> a, int n_below, int last)
         C *= gl[l];
     }
     // hand over to canonical order: slot of the particle at each position.  With FP32 state
-    // and at least four particles per lane the velocities and pids also move to their
+    // and at least three particles per lane the velocities and pids also move to their
     // canonical lanes through the sort's LDS instead of a second global read (measured
-    // 4.41 -> 4.08 ms on channel_large); with FP64 state the extra live registers spill
-    // (4.69 -> 4.82 ms) and with three per lane it was slower too (24.6 -> 25.2 ms on the
-    // street canyon), so the global read is kept there.
-    constexpr bool PERM = sizeof(R) == sizeof(float) && PPL >= 4;
+    // 4.41 -> 4.08 ms on channel_large, 23.9 -> 19.6 ms on the large street canyon once the
+    // lanes sum their particles plainly); with FP64 state the extra live registers spill
+    // (4.69 -> 4.82 ms), so the global read is kept there, and so it is for three per lane
+    // with the projection, whose registers would spill.
+    constexpr bool PERM = sizeof(R) == sizeof(float) && (PPL >= 4 || (PPL == 3 && !PROJ));
 #pragma unroll
     for (int r = 0; r < PPL; ++r)
         if (lane + 64 * r < n) ord[pos[r]] = gi[r];
@@ -1451,7 +1469,9 @@ k_element_wave(ElementArgs<R> a, int n_below, int last)
     for (int v = 0; v < 3; ++v)
 #pragma unroll
         for (int q = 0; q < 5; ++q) rs[v][q] = a.shift[(int64_t)G->node[v] * 5 + q];
-    Acc<R> acc[3][NPART];
+    // each lane adds its (at most PPL) particles plainly; the 64 lane sums are added with Acc
+    // below (Kahan-compensated in FP32)
+    LaneSum<R> acc[3][NPART];
 #pragma unroll
     for (int r = 0; r < PPL; ++r) {
         const int p = lane + 64 * r;
