@@ -34,6 +34,8 @@ struct AdvanceArgs {
     int32_t* wave_list;         // [wave_cap] wavefronts whose lanes hold several problems
     int32_t* wave_count;
     int64_t wave_cap;
+    int32_t* redo_list;         // [cap] slots for the full particle loop (walks that reach a wall)
+    int32_t* redo_count;
     int64_t ne;
     ProbParams p0;              // parameters of problem 0 (single-problem ensembles)
     const ProbParams* prm;      // [n_problems] (batched ensembles)

@@ -64,11 +64,14 @@ struct AdvEvents {
 };
 
 // One particle of the particle loop with the parameters P of its problem.  Returns its new
-// host element (its old one when it could not be tracked).  R = double: FP64 throughout;
+// host element (its old one when it could not be tracked).  DEFER: a particle whose walk
+// reaches a wall or free-slip edge is left untouched and -2 returned, for the full loop of
+// k_advance_redo (the fall-back search and the reflections are rare, and their call and
+// registers would set the budget of the whole loop).  R = double: FP64 throughout;
 // R = float: velocity, frequency and their SDEs in FP32, positions and tracking in FP64.
 // WPFULL: the nodal wp field has all nine components (stored by the elliptic-relaxation
 // solve); otherwise it is symmetric and the three lower components are not read
-template <class R, bool WPFULL, class PP>
+template <class R, bool WPFULL, bool DEFER, class PP>
 __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const int64_t i, const int32_t e,
                                                const uint32_t step, AdvEvents& ev, const PP& P)
 {
@@ -224,6 +227,7 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
             ++ev.steps;
             continue;
         }
+        if constexpr (DEFER) return -2;
         int32_t fe;
         double off;
         if (fallback_search(a.geo, a.n2e_ptr, a.n2e, c, x, y, fe, off)) {
@@ -390,7 +394,7 @@ __device__ __forceinline__ int arrival_rank(const HostCount& h) { return __shfl(
 // index of the lane, slots beyond the used ones are idle lanes.  PM_WAVE: a wavefront whose
 // live lanes hold more than one problem does nothing here and is listed for
 // k_advance_mixed_waves, which runs it with PM_LANE.
-template <class R, int PM, bool WPFULL>
+template <class R, int PM, bool WPFULL, bool DEFER>
 __device__ __forceinline__ void particle_slot(const AdvanceArgs<R>& a, const int64_t i)
 {
     const int64_t nslots = a.meta[0];
@@ -407,13 +411,13 @@ __device__ __forceinline__ void particle_slot(const AdvanceArgs<R>& a, const int
         }
         if constexpr (PM == PM_ONE) {
             if (e >= 0) {
-                key = advance_one<R, WPFULL>(a, i, e, step, ev, a.p0);
+                key = advance_one<R, WPFULL, DEFER>(a, i, e, step, ev, a.p0);
                 prob = 0;
             }
         } else if constexpr (PM == PM_LANE) {
             if (e >= 0) {
                 prob = a.geo[e].prob;
-                key = advance_one<R, WPFULL>(a, i, e, step, ev, *(ConstProb*)(a.prm + prob));
+                key = advance_one<R, WPFULL, DEFER>(a, i, e, step, ev, *(ConstProb*)(a.prm + prob));
             }
         }
     }
@@ -430,8 +434,25 @@ __device__ __forceinline__ void particle_slot(const AdvanceArgs<R>& a, const int
             return;
         }
         if (e >= 0) {
-            key = advance_one<R, WPFULL>(a, i, e, step, ev, *(ConstProb*)(a.prm + pu));
+            key = advance_one<R, WPFULL, DEFER>(a, i, e, step, ev, *(ConstProb*)(a.prm + pu));
             prob = pu;
+        }
+    }
+    if constexpr (DEFER) {
+        // particles left to k_advance_redo: listed (one atomic per wavefront), nothing counted
+        const bool redo = key == -2;
+        if (redo) {
+            key = -1;
+            prob = -1;
+            ev = AdvEvents{0, 0, 0, 0, 0, 0, 0, 0, 0};
+        }
+        const unsigned long long rb = __ballot(redo);
+        if (rb) {
+            const int lane = lane_id();
+            int base = 0;
+            if (lane == 0) base = atomicAdd(a.redo_count, __popcll(rb));
+            base = __shfl(base, 0);
+            if (redo) a.redo_list[base + __popcll(rb & ((1ull << lane) - 1ull))] = (int32_t)i;
         }
     }
     // slots whose frequency is drawn again: one atomic per wavefront
@@ -450,24 +471,26 @@ __device__ __forceinline__ void particle_slot(const AdvanceArgs<R>& a, const int
     if (key >= 0) a.arrival[i] = arrival;
 }
 
-// One problem: three wavefronts per SIMD in the FP64 form (at most 168 registers; four
-// spill: 8.0 against 5.2 ms on the 8e7-particle channel), four in the mixed form (at most
-// 128 registers: 3.86 against 4.23 ms with three).
+// One problem: four wavefronts per SIMD (at most 128 registers).  With the fall-back search
+// and the reflections left to k_advance_redo the FP64 loop needs 132 registers (two spill
+// at four: 4.91 ms on the 8e7-particle channel against 5.29 ms at three; 5.17 ms at three
+// with that code in the loop, whose call took 158 registers and spilled 29 at four, 8.0 ms);
+// the mixed loop fits 124 (3.63 against 3.86 ms with the code in the loop).
 template <class R, bool WPFULL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == sizeof(float) ? 4 : 3)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_advance(AdvanceArgs<R> a)
 {
-    particle_slot<R, PM_ONE, WPFULL>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    particle_slot<R, PM_ONE, WPFULL, true>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Several problems: the wavefronts whose lanes share one problem (all but those across the
 // ends of the problems' slot ranges, and some among the clones of number control) read its
 // parameters as scalars, which keeps the register budget of the one-problem loop
 template <class R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == sizeof(float) ? 4 : 3)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_advance_batched(AdvanceArgs<R> a)
 {
-    particle_slot<R, PM_WAVE, false>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    particle_slot<R, PM_WAVE, false, true>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ... and the listed wavefronts with each lane's parameters from the table (one wavefront per
@@ -477,7 +500,21 @@ __global__ void __launch_bounds__(64) k_advance_mixed_waves(AdvanceArgs<R> a)
 {
     const int n = (int)min((int64_t)*a.wave_count, a.wave_cap);
     for (int w = blockIdx.x; w < n; w += gridDim.x)
-        particle_slot<R, PM_LANE, false>(a, (int64_t)a.wave_list[w] * 64 + threadIdx.x);
+        particle_slot<R, PM_LANE, false, false>(a, (int64_t)a.wave_list[w] * 64 + threadIdx.x);
+}
+
+// The particles whose walk reached a wall or free-slip edge in k_advance or
+// k_advance_batched, advanced again from their unchanged start-of-step state by the full
+// loop (fall-back search of Sec. 3.6, reflections of Sec. 3.8): the same counter-based random
+// numbers give the same step.  One wavefront per workgroup, grid-stride over the list.
+template <class R, int PM, bool WPFULL>
+__global__ void __launch_bounds__(64) k_advance_redo(AdvanceArgs<R> a)
+{
+    const int64_t n = *a.redo_count;
+    for (int64_t b = (int64_t)blockIdx.x * 64; b < n; b += (int64_t)gridDim.x * 64) {
+        const int64_t j = b + threadIdx.x;
+        particle_slot<R, PM, WPFULL, false>(a, j < n ? (int64_t)a.redo_list[j] : INT64_MAX);
+    }
 }
 
 // Eq. (58) for the particles of the last no-slip events: omega ~ Gamma(1/C4) with the mean
@@ -1534,6 +1571,7 @@ __global__ void __launch_bounds__(256) k_node_finalize(NodeArgs<R> a)
         a.big_count[0] = 0;          // worklist of large elements, empty for the next pass
         a.big_count[1] = 0;          // list of no-slip resamples, empty for the next step
         a.big_count[2] = 0;          // list of wavefronts with several problems, the same
+        a.big_count[3] = 0;          // list of particles for the full particle loop, the same
     }
     if (i >= a.nn) return;
     if (a.estimator == 1) {
@@ -2040,14 +2078,18 @@ void launch_advance(const AdvanceArgs<R>& a, int64_t n_ub, bool batched, bool wp
 {
     if (n_ub <= 0) return;
     if (block != 64 && block != 128) block = 256;
+    const unsigned small = (unsigned)std::min<int64_t>((n_ub + 63) / 64, 1024);
     if (batched) {
         hipLaunchKernelGGL(k_advance_batched<R>, dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
-        const int64_t waves = (n_ub + 63) / 64;
-        hipLaunchKernelGGL(k_advance_mixed_waves<R>, dim3((unsigned)std::min<int64_t>(waves, 1024)), dim3(64), 0, s, a);
-    } else if (wp_full)
+        hipLaunchKernelGGL(k_advance_mixed_waves<R>, dim3(small), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_advance_redo<R, PM_LANE, false>), dim3(small), dim3(64), 0, s, a);
+    } else if (wp_full) {
         hipLaunchKernelGGL((k_advance<R, true>), dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
-    else
+        hipLaunchKernelGGL((k_advance_redo<R, PM_ONE, true>), dim3(small), dim3(64), 0, s, a);
+    } else {
         hipLaunchKernelGGL((k_advance<R, false>), dim3(blocks_for(n_ub, block)), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_advance_redo<R, PM_ONE, false>), dim3(small), dim3(64), 0, s, a);
+    }
     hipLaunchKernelGGL(k_wall_resample<R>, dim3(256), dim3(256), 0, s, a.s, (const int32_t*)a.wall_list,
                        (const int32_t*)a.wall_count, a.geo, a.prm, a.meta);
 }

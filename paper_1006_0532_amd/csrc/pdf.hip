@@ -226,6 +226,8 @@ pdf_status step_once(pdf_ens_s* E, hipStream_t s)
     a.wave_list = E->wave_list;
     a.wave_count = E->big_count + 2;
     a.wave_cap = E->n_problems > 1 ? E->cap / 64 + 2 : 0;
+    a.redo_list = E->gord;         // element-pass scratch, free during the particle loop
+    a.redo_count = E->big_count + 3;
     a.ne = g.ne;
     a.p0 = E->h_prm[0];
     a.prm = E->d_prm;
@@ -1192,7 +1194,7 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
     if (st == PDF_OK) st = dalloc(&E->ctl_off, g.ne + 1);
     if (st == PDF_OK) st = dalloc(&E->ctl_rep, 4);
     if (st == PDF_OK) st = dalloc(&E->big_list, g.ne);
-    if (st == PDF_OK) st = dalloc(&E->big_count, 3);
+    if (st == PDF_OK) st = dalloc(&E->big_count, 4);
     if (st == PDF_OK && n_problems > 1) st = dalloc(&E->wave_list, cap / 64 + 2);
     if (st != PDF_OK) {
         pdf_ens_destroy(E);
@@ -1217,7 +1219,7 @@ pdf_status pdf_particles_init(const pdf_grid* grids, const pdf_init_desc* descs,
         return st;
     }
     launch_fill_i32(E->counts, g.ne, 0, s);
-    launch_fill_i32(E->big_count, 3, 0, s);
+    launch_fill_i32(E->big_count, 4, 0, s);
     launch_fill_i32(E->idx, cap, 0, s);
     launch_fill_u64(E->cnt, (int64_t)n_problems * NCOUNT * CNT_SLOTS, 0ull, s);
     launch_fill_i32(reinterpret_cast<int32_t*>(E->err), 1, 0, s);

@@ -218,7 +218,8 @@ struct pdf_ens_s {
     int64_t g_nub[2] = {-1, -1};
     std::vector<double> g_dt[2];
     int32_t* big_list = nullptr;    // [ne] elements left to the workgroup kernel
-    int32_t* big_count = nullptr;   // [3] large elements, no-slip resamples, wavefronts of several problems
+    int32_t* big_count = nullptr;   // [4] large elements, no-slip resamples, wavefronts of several problems,
+                                    // particles for the full particle loop
     int32_t* wave_list = nullptr;   // [cap / 64 + 2] wavefronts of several problems (batched ensembles)
     int ppl_min = 1;                // wavefront capacity suggested by the smallest set-up count
     std::vector<int> tiers;         // particles per lane of the wavefront tiers, ascending
