@@ -229,6 +229,34 @@ def test_walls_slip_and_multistep_walks(gpu):
     assert c == oe.counters()
 
 
+def test_most_walks_reach_a_wall(gpu):
+    """A strong wall-normal mean flow and large steps send more than 65 536 of 1.9e5
+    particles across the free-slip top wall in one step, so the list of walks that reach a
+    wall (advanced again by the full loop) is longer than one pass of that kernel's grid;
+    states after every step, statistics and counters equal the oracle's."""
+    _say("test_most_walks_reach_a_wall")
+    mesh = box(20, 24, length=2.0, jitter=0.1, seed=17, bottom=W.EDGE_WALL, top=W.EDGE_SLIP)
+    f = W.uniform_fields(mesh, mean_u=(0.3, 2.5, 0.0), mean_omega=2.0)
+    mo = W.model_constants(nu=1e-4)
+    ini = W.init_desc(ppe=200, u_sigma=0.3, src_x=1.0, src_r=0.3, bins=(3, 2, 1), seed=0x3A11)
+    og, oe, gg, ge = _pair(gpu, mesh, f, mo, ini)
+    frame = og.export()["frame"]
+    excl = set()
+    for dt in (0.35, 0.02, 0.02, 0.3):
+        before = ge.counters()
+        oe.step(dt)
+        ge.step(dt)
+        c = ge.counters()
+        assert c == oe.counters()
+        refl = c["reflections"] - before["reflections"]
+        if dt > 0.1:
+            assert refl > 65536, (dt, refl)
+        rep, excl = compare_states(ge.export(), oe.export(), frame, _length(mesh), excl)
+        _say(f"  dt {dt}: {refl} reflections; {rep}")
+    skip = set(mesh.tri[list(excl)].ravel().tolist()) if excl else set()
+    compare_stats(ge.stats(), oe.stats(), skip)
+
+
 def test_no_slip_events(gpu):
     """Near-wall particles: trajectories (a) and (b) with Gamma frequency resampling."""
     _say("test_no_slip_events")
