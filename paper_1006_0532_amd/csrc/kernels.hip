@@ -293,13 +293,17 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
         omn = omw;
         ev.resample = 1;
     }
-    a.s.x[i] = x;
-    a.s.y[i] = y;
-    a.s.u0[i] = v0;
-    a.s.u1[i] = v1;
-    a.s.u2[i] = v2;
-    a.s.om[i] = omn;
-    a.s.elem[i] = c;
+    // the slot index passes through an empty asm statement, so that the store addresses are
+    // formed here instead of being kept in registers from the loads at the start
+    int64_t io = i;
+    asm volatile("" : "+v"(io));
+    a.s.x[io] = x;
+    a.s.y[io] = y;
+    a.s.u0[io] = v0;
+    a.s.u1[io] = v1;
+    a.s.u2[io] = v2;
+    a.s.om[io] = omn;
+    a.s.elem[io] = c;
     if (P.src_cont) {
         double dx = x - P.src_x, dy = y - P.src_y;
         if (P.period > 0.0) {
@@ -307,7 +311,7 @@ __device__ __forceinline__ int32_t advance_one(const AdvanceArgs<R>& a, const in
             else if (dx < -0.5 * P.period) dx += P.period;
         }
         if (dx * dx + dy * dy < P.src_r2) {
-            a.s.psi[i] = R(1);
+            a.s.psi[io] = R(1);
             ev.src = 1;
         }
     }
