@@ -682,19 +682,35 @@ __global__ void __launch_bounds__(256) k_scatter(const int32_t* __restrict__ ele
 
 // Slot of every live particle inside its element's segment from the arrival ranks of the
 // particle loop (no atomics); the counts are cleared separately.
+__device__ __forceinline__ void place_one(const int32_t* __restrict__ start, int32_t* __restrict__ idx,
+                                          uint32_t* __restrict__ err, int64_t ne, int64_t i, int32_t e, int32_t r)
+{
+    if (e < 0 || e >= ne) return;
+    const int64_t lo = start[e], hi = start[e + 1];
+    const int64_t slot = lo + (int64_t)r;
+    if (slot >= lo && slot < hi) idx[slot] = (int32_t)i;
+    else atomicOr(err, ERR_BADELEM);
+}
+
+// four slots per thread, read as one 16-byte load of each array
 __global__ void __launch_bounds__(256) k_place(const int32_t* __restrict__ elem, const int32_t* __restrict__ arrival,
                                                const int64_t* __restrict__ nslots, int64_t n_ub, int64_t ne,
                                                const int32_t* __restrict__ start, int32_t* __restrict__ idx,
                                                uint32_t* __restrict__ err)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n_ub || i >= *nslots) return;
-    const int32_t e = elem[i];
-    if (e < 0 || e >= ne) return;
-    const int64_t lo = start[e], hi = start[e + 1];
-    const int64_t slot = lo + (int64_t)arrival[i];
-    if (slot >= lo && slot < hi) idx[slot] = (int32_t)i;
-    else atomicOr(err, ERR_BADELEM);
+    const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    const int64_t n = min(n_ub, *nslots);
+    if (i0 >= n) return;
+    if (i0 + 4 <= n) {
+        const int4 e4 = *reinterpret_cast<const int4*>(elem + i0);
+        const int4 r4 = *reinterpret_cast<const int4*>(arrival + i0);
+        place_one(start, idx, err, ne, i0, e4.x, r4.x);
+        place_one(start, idx, err, ne, i0 + 1, e4.y, r4.y);
+        place_one(start, idx, err, ne, i0 + 2, e4.z, r4.z);
+        place_one(start, idx, err, ne, i0 + 3, e4.w, r4.w);
+    } else {
+        for (int64_t i = i0; i < n; ++i) place_one(start, idx, err, ne, i, elem[i], arrival[i]);
+    }
 }
 
 // =====================================================================================
@@ -2128,8 +2144,8 @@ void launch_place(const int32_t* elem, const int32_t* arrival, const int64_t* ns
                   const int32_t* start, int32_t* idx, uint32_t* err, hipStream_t s)
 {
     if (n_ub > 0)
-        hipLaunchKernelGGL(k_place, dim3(blocks_for(n_ub, 256)), dim3(256), 0, s, elem, arrival, nslots, n_ub, ne,
-                           start, idx, err);
+        hipLaunchKernelGGL(k_place, dim3(blocks_for((n_ub + 3) / 4, 256)), dim3(256), 0, s, elem, arrival, nslots, n_ub,
+                           ne, start, idx, err);
 }
 template <class R>
 hipError_t prepare_element_pass(int lds_max)
