@@ -104,6 +104,9 @@ def parse():
                    help="set up the channel, take the warm-up steps, then run only the Eulerian solves "
                         "and the closed loop and print their figures")
     p.add_argument("--batched-problems", type=int, default=64)
+    p.add_argument("--batched-only", choices=("batched", "plain"), default=None,
+                   help="run only the batched problems in FP64, as one ensemble or one ensemble at a time "
+                        "(for per-kernel profiles of the two), and print their figures")
     return p.parse_args()
 
 
@@ -307,7 +310,7 @@ def mixed_error(mesh, f, mo, ini, dt, steps):
     return err
 
 
-def batched_form(args):
+def batched_form(args, legs=("fp64", "mixed", "plain")):
     """64 independent channel / street-canyon problems of uneven size (triangles
     log-uniform in [1e3, 2e5], 20-400 particles per element): advanced together (one
     launch per kernel, the particle loop's wavefronts across the ends of two problems in a
@@ -323,6 +326,8 @@ def batched_form(args):
     out = {"problems": len(probs), "triangles": int(sum(m.n_elems for m, *_ in probs)), "particles": int(n_total),
            "steps": args.form_steps}
     for name, prec in (("fp64", pdfgpu.PDF_FP64), ("mixed", pdfgpu.PDF_MIXED)):
+        if name not in legs:
+            continue
         ens = pdfgpu.Ensemble(grids, inits, capacity=caps, precision=prec)
         ens.set_options(use_graph=1)
         chosen, trials = ens.autotune(dts, steps_per_trial=2)
@@ -330,6 +335,10 @@ def batched_form(args):
         out[name] = {"value": live / el, "ms_per_step": 1e3 * el / args.form_steps, "options": chosen,
                      "autotune_trial_ms": [round(t, 3) for t in trials]}
         ens.close()
+    if "plain" not in legs:
+        for g in grids:
+            g.close()
+        return out
     # the same FP64 problems one ensemble at a time (seed ^ p << 32 gives the same streams)
     live_tot, el_tot = 0, 0.0
     for p, (g, ini, dt, cap) in enumerate(zip(grids, inits, dts, caps)):
@@ -397,6 +406,10 @@ def main():
     torch.cuda.set_device(0)
     if args.large_mixed_only:
         print(json.dumps(large_mixed_form(args)), flush=True)
+        return
+    if args.batched_only:
+        legs = ("fp64",) if args.batched_only == "batched" else ("plain",)
+        print(json.dumps(batched_form(args, legs)), flush=True)
         return
     if args.copy_calib:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
