@@ -475,11 +475,12 @@ __device__ __forceinline__ void particle_slot(const AdvanceArgs<R>& a, const int
     if (key >= 0) a.arrival[i] = arrival;
 }
 
-// One problem: four wavefronts per SIMD (at most 128 registers).  With the fall-back search
-// and the reflections left to k_advance_redo the FP64 loop needs 132 registers (two spill
-// at four: 4.91 ms on the 8e7-particle channel against 5.29 ms at three; 5.17 ms at three
-// with that code in the loop, whose call took 158 registers and spilled 29 at four, 8.0 ms);
-// the mixed loop fits 124 (3.63 against 3.86 ms with the code in the loop).
+// One problem: at least four wavefronts per SIMD (at most 128 registers).  With the fall-back
+// search and the reflections left to k_advance_redo and the store addresses formed at the
+// stores, the FP64 loop needs 114 registers (4.7 ms on the 8e7-particle channel; 5.17 ms at
+// three wavefronts with that code in the loop, whose call took 158 registers and spilled 29
+// at four, 8.0 ms) and the mixed loop 90, five wavefronts (3.35 ms; 3.86 ms at four with the
+// code in the loop).
 template <class R, bool WPFULL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_advance(AdvanceArgs<R> a)
