@@ -482,14 +482,16 @@ int ppl_for(int64_t ppe)
     return p == 7 ? 8 : p;
 }
 
-// wavefront tiers from the smallest suggested capacity, doubling, up to ppl
+// wavefront tiers from the smallest suggested capacity up to ppl: doubling to 4 particles
+// per lane, then 6 and 8 (an element is taken by the smallest tier that holds it; between 4
+// and 8 a tier of 6 keeps three wavefronts per SIMD in FP64 where 8 allows two)
 void set_tiers(pdf_ens_s* E)
 {
     E->tiers.clear();
     int t = std::min(E->ppl_min, E->ppl);
-    while (t < E->ppl && (int)E->tiers.size() < 3) {
+    while (t < E->ppl) {
         E->tiers.push_back(t);
-        t = t * 2 == 7 ? 8 : std::min(t * 2, 8);
+        t = t < 4 ? 2 * t : (t < 6 ? 6 : 8);
     }
     E->tiers.push_back(E->ppl);
 }
