@@ -206,16 +206,16 @@ def timed_steps(ens, dt, steps, ctl=None):
     import torch
     ens.sync()
     torch.cuda.synchronize()
-    n_fixed = None if ctl else ens.count()     # without control the live count is constant
+    cur = ens.count()     # then from each control report; without control it is constant
     live, t0 = 0, time.perf_counter()
     if ctl:
         for _ in range(steps):
-            live += ens.count()
+            live += cur
             ens.step(dt)
-            ens.control(*ctl)
+            cur = ens.control(*ctl)["live"]
     else:
         ens.step(dt, steps)
-        live = n_fixed * steps
+        live = cur * steps
     ens.sync()
     torch.cuda.synchronize()
     return live, time.perf_counter() - t0
@@ -475,14 +475,17 @@ def main():
         print(json.dumps({"workload": "channel_large", "eulerian": eulerian_leg(ens, dt, ctl)}), flush=True)
         return
 
+    # the live count of each step: the first from pdf_count before the timed region, the
+    # others from the previous step's control report (one synchronisation per step)
     live = []
+    cur = ens.count()
     ens.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        live.append(ens.count())
+        live.append(cur)
         ens.step(dt)
-        ens.control(*ctl)
+        cur = ens.control(*ctl)["live"]
     ens.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -565,6 +568,8 @@ def main():
         forms["batched"] = batched_form(args)
         b = forms["batched"]
         b["speedup_vs_plain"] = b["fp64"]["value"] / b["plain_fp64_one_at_a_time"]["value"]
+        # against the channel's FP64 rate above (smaller problems, half of them street canyons)
+        b["rate_vs_channel_fp64"] = b["fp64"]["value"] / value
         print(f"[bench] batched: {json.dumps(b)}", file=sys.stderr, flush=True)
         forms["cavity_huge_mixed"] = large_mixed_form(args)
         print(f"[bench] cavity_huge mixed: {json.dumps(forms['cavity_huge_mixed'])}", file=sys.stderr, flush=True)
