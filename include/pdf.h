@@ -294,8 +294,8 @@ pdf_status pdf_set_feedback(pdf_ens ens, int32_t enable, double alpha, int32_t f
  * *moves_out (may be NULL) receives the number of moves.  Synchronises.
  * Errors: PDF_E_INVAL (n_min < 0, bad problem), PDF_E_STATE (no step since the last
  * control or redistribution), PDF_E_CAPACITY (a problem whose counts span more than 2^22
- * levels on the giving side, or whose level table exceeds 2^27 entries), PDF_E_NOMEM,
- * PDF_E_HIP. */
+ * levels, or whose elements times the count levels one side visits exceed 2^31 - 1),
+ * PDF_E_NOMEM, PDF_E_HIP. */
 pdf_status pdf_redistribute(pdf_ens ens, int32_t problem, int32_t n_min, int64_t* moves_out,
                             void* hip_stream);
 

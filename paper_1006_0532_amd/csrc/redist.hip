@@ -39,9 +39,8 @@ namespace {
 
 constexpr uint32_t TAG_REDIST = 5;
 constexpr int RD_NT = 256;
-// limits of the level tables: levels visited by one side, and workgroups x levels entries
+// limit of the level histograms: count levels one side can visit
 constexpr int64_t RD_MAX_LEVELS = 1 << 22;
-constexpr int64_t RD_MAX_TABLE = int64_t(1) << 27;
 
 unsigned rd_blocks(int64_t n) { return (unsigned)((n + RD_NT - 1) / RD_NT); }
 
@@ -280,8 +279,9 @@ pdf_status enumerate_side(Scratch& sc, const RdProblem& q, int sgn, int32_t L, c
                           int32_t*& key, int32_t*& off, int32_t*& list, hipStream_t s)
 {
     const int64_t ne = q.ne, nb = rd_blocks(ne);
-    if (nb * (int64_t)L > RD_MAX_TABLE) {
-        set_error("redistribution: the level table of one problem exceeds its limit (elements x levels)");
+    // the (element, level) pairs are listed with 32-bit offsets: ne x L bounds their number
+    if (ne * (int64_t)L > INT32_MAX) {
+        set_error("redistribution: one problem's elements times the levels one side visits exceed 2^31 - 1");
         return PDF_E_CAPACITY;
     }
     int32_t *len = nullptr, *tmp = nullptr, *T = nullptr;
@@ -344,7 +344,8 @@ pdf_status redistribution_plan(pdf_ens_s* E, const std::vector<int>& problems, i
         q.lmin = h_mm[0];
         q.cmax = h_mm[1];
         if (q.lmin >= n_min || q.cmax - q.lmin <= 1) continue;
-        const int64_t nlo = (int64_t)n_min - q.lmin;
+        // the receiving side stays below n_min and below cmax - 1, the giving side above lmin + 1
+        const int64_t nlo = std::min<int64_t>((int64_t)std::min(n_min, q.cmax) - q.lmin, RD_MAX_LEVELS);
         const int64_t nhi = std::min<int64_t>((int64_t)q.cmax - q.lmin + 1, RD_MAX_LEVELS);
         int32_t *hlo = nullptr, *hhi = nullptr;
         st = sc.get(&hlo, nlo);
@@ -367,8 +368,8 @@ pdf_status redistribution_plan(pdf_ens_s* E, const std::vector<int>& problems, i
         q.Slo.push_back(0);
         q.Shi.push_back(0);
         while (!(l >= n_min || h - l <= 1)) {
-            if (q.cmax - h >= nhi) {
-                set_error("redistribution: the giving side would visit more count levels than its limit");
+            if (q.cmax - h >= nhi || l - q.lmin >= nlo) {
+                set_error("redistribution: one side would visit more count levels than its limit");
                 return PDF_E_CAPACITY;
             }
             const int64_t Pt = Hlo[l - q.lmin], Qt = Hhi[q.cmax - h];
