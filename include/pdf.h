@@ -214,7 +214,8 @@ pdf_status pdf_step(pdf_ens ens, const double* dt, int32_t n_steps, void* hip_st
  * k selected statistics in ascending j.  A mask that selects none or has bits above 12 is
  * PDF_E_INVAL.
  * out_is_device != 0: out is a device pointer and the copy is enqueued on hip_stream;
- * otherwise out is host memory and the call synchronises. */
+ * otherwise out is host memory and the call synchronises (a subset of the columns is
+ * selected on the device, in a temporary allocated for the call: PDF_E_NOMEM if it fails). */
 pdf_status pdf_stats(pdf_ens ens, int32_t problem, uint32_t stat_mask, double* out, int32_t out_is_device,
                      void* hip_stream);
 

@@ -1338,14 +1338,26 @@ pdf_status pdf_stats(pdf_ens E, int32_t problem, uint32_t stat_mask, double* out
         HIP_TRY(hipStreamSynchronize(s));
         return check_device_error(E);
     }
-    std::vector<double> all((size_t)P.nn * NSTAT);
-    HIP_TRY(hipMemcpyAsync(all.data(), src, sizeof(double) * all.size(), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    for (int64_t n = 0; n < P.nn; ++n) {
-        int c = 0;
-        for (int j = 0; j < NSTAT; ++j)
-            if ((stat_mask >> j) & 1u) out[n * k + c++] = all[(size_t)n * NSTAT + j];
+    // a subset of the columns: selected on the device into a temporary, then copied
+    if (P.nn == 0) return check_device_error(E);
+    struct Tmp {
+        double* p = nullptr;
+        ~Tmp()
+        {
+            if (p) (void)hipFree(p);
+        }
+    } tmp;
+    if (hipMalloc((void**)&tmp.p, sizeof(double) * (size_t)P.nn * k) != hipSuccess) {
+        (void)hipGetLastError();
+        tmp.p = nullptr;
+        set_error("pdf_stats: device allocation of the selected columns failed");
+        return PDF_E_NOMEM;
     }
+    hipLaunchKernelGGL(k_stats_select, dim3((unsigned)((P.nn * k + 255) / 256)), dim3(256), 0, s, src, P.nn, stat_mask,
+                       k, tmp.p);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, tmp.p, sizeof(double) * (size_t)P.nn * k, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     return check_device_error(E);
 }
 
