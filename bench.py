@@ -7,9 +7,9 @@ Prints one JSON line with whole-job throughput, the roofline of the dominant ker
 (timed with HIP events on the ensemble's stream), the CPU oracle timed on a bounded
 sample of the same workload, and the other forms: the same workload in mixed precision
 (with its statistics against the FP64 form on the channel and on the 10^8-particle street
-canyon, each field against its bound), 64 uneven independent problems advanced as one batched ensemble against the same problems
-advanced one at a time, and the large street canyon (4e6 triangles, about 4.8e8
-particles) in mixed precision with per-kernel HBM rates.
+canyon, each field against its bound), 64 uneven independent problems advanced as one
+batched ensemble against the same problems advanced one at a time, and the large street
+canyon (4e6 triangles, about 4.8e8 particles) in mixed precision with per-kernel HBM rates.
 """
 from __future__ import annotations
 
